@@ -1,0 +1,248 @@
+"""Seeded synthetic inputs for the variational Stokes step.
+
+This module only *generates inputs*: level sets at grid nodes, cell-centred
+density and viscosity, face velocities, prescribed solid velocities, gravity.
+It contains none of the method's arithmetic (no fractions, no operators, no
+solve), so both the CPU oracle tests and the GPU path can consume the same
+arrays without sharing any computation.
+
+Conventions (used by every consumer):
+  * index order [i, j(, k)] = (x, y(, z)); arrays flatten x-fastest with
+    ``np.ravel(order="F")``;
+  * grid of nx*ny(*nz) cells of size h, box [origin, origin + n*h];
+  * nodal level sets have shape (nx+1, ny+1(, nz+1)); phi < 0 is inside;
+  * face arrays: u (nx+1, ny(, nz)), v (nx, ny+1(, nz)), w (nx, ny, nz+1);
+  * cell arrays (rho, mu): (nx, ny(, nz)).
+
+Workloads (one base seed each, recorded by the caller):
+  config1  2D 32^2 drop above a solid floor, FP64 reference case.
+  config2  2D 512^2 pool + 8 random circles + moving solid disc,
+           smooth log-uniform viscosity [1,1000] and density [0.5,2].
+  config3  3D 128^2 falling column with perturbed radius onto a floor.
+  config4  64 independent 2D problems, n in {64,96,...,512}, each shaped as
+           config1 with its own seed.
+  config5  3D 256^3 analogue of config2 (pool + 8 spheres + moving sphere).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "node_coords", "face_coords", "cell_coords",
+    "config1", "config2", "config3", "config4", "config5", "make_config",
+    "drop2d", "pool2d", "pool3d", "column3d",
+]
+
+
+# --------------------------------------------------------------------------
+# coordinates
+# --------------------------------------------------------------------------
+def _axis(n, h, o, staggered_half):
+    k = np.arange(n, dtype=np.float64)
+    return o + (k + (0.5 if staggered_half else 0.0)) * h
+
+
+def node_coords(n, h, origin):
+    """Coordinates of grid nodes, one meshgrid array per axis (ij indexing)."""
+    axes = [_axis(n[a] + 1, h, origin[a], False) for a in range(len(n))]
+    return np.meshgrid(*axes, indexing="ij")
+
+
+def cell_coords(n, h, origin):
+    axes = [_axis(n[a], h, origin[a], True) for a in range(len(n))]
+    return np.meshgrid(*axes, indexing="ij")
+
+
+def face_coords(n, h, origin, axis):
+    """Coordinates of the faces normal to ``axis`` (MAC velocity samples)."""
+    axes = []
+    for a in range(len(n)):
+        if a == axis:
+            axes.append(_axis(n[a] + 1, h, origin[a], False))
+        else:
+            axes.append(_axis(n[a], h, origin[a], True))
+    return np.meshgrid(*axes, indexing="ij")
+
+
+def face_shapes(n):
+    d = len(n)
+    return [tuple(n[b] + (1 if b == a else 0) for b in range(d)) for a in range(d)]
+
+
+# --------------------------------------------------------------------------
+# smooth random fields
+# --------------------------------------------------------------------------
+def _gauss_field(rng, X, count=4):
+    """Sum of ``count`` random Gaussians, min-max normalised to [0, 1]."""
+    d = len(X)
+    s = np.zeros_like(X[0])
+    for _ in range(count):
+        a = rng.uniform(0.5, 1.0)
+        m = rng.uniform(0.0, 1.0, size=d)
+        sig = rng.uniform(0.1, 0.3)
+        r2 = sum((X[q] - m[q]) ** 2 for q in range(d))
+        s = s + a * np.exp(-r2 / (2.0 * sig * sig))
+    lo, hi = s.min(), s.max()
+    return (s - lo) / (hi - lo) if hi > lo else np.zeros_like(s)
+
+
+def _case(dim, n, h, origin, dt, phi_l, phi_s, rho, mu, u, u_bc, g, **meta):
+    c = dict(dim=dim, n=tuple(int(q) for q in n), h=float(h),
+             origin=tuple(float(o) for o in origin), dt=float(dt),
+             phi_l=phi_l, phi_s=phi_s, rho=rho, mu=mu, u=list(u),
+             u_bc=None if u_bc is None else list(u_bc), g=tuple(float(q) for q in g))
+    c.update(meta)
+    return c
+
+
+# --------------------------------------------------------------------------
+# 2D drop above a floor (config 1, and each member of config 4)
+# --------------------------------------------------------------------------
+def drop2d(n, seed, dt=0.01, radius=0.35, centre=(0.5, 0.5), floor=0.1,
+           sigma=0.1, rho=1.0, mu=1.0, g=(0.0, -1.0)):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    nn = (n, n)
+    X, Y = node_coords(nn, h, (0.0, 0.0))
+    phi_l = np.hypot(X - centre[0], Y - centre[1]) - radius
+    phi_s = Y - floor
+    u = [rng.normal(0.0, sigma, size=s) for s in face_shapes(nn)]
+    return _case(2, nn, h, (0.0, 0.0), dt, phi_l, phi_s,
+                 np.full(nn, rho), np.full(nn, mu), u, None, g,
+                 name=f"drop2d_{n}", seed=seed)
+
+
+def config1(seed=1):
+    c = drop2d(32, seed)
+    c.update(name="config1", tol=1e-10, precision="fp64")
+    return c
+
+
+# --------------------------------------------------------------------------
+# 2D pool with random circles and a moving disc (config 2)
+# --------------------------------------------------------------------------
+def pool2d(n, seed, dt=1e-3, n_circles=8, depth=0.3, g=(0.0, -1.0)):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    nn = (n, n)
+    X, Y = node_coords(nn, h, (0.0, 0.0))
+    phi_l = Y - depth
+    for _ in range(n_circles):
+        r = rng.uniform(0.05, 0.2)
+        cx = rng.uniform(r, 1.0 - r)
+        cy = rng.uniform(depth + r, 1.0 - r)
+        phi_l = np.minimum(phi_l, np.hypot(X - cx, Y - cy) - r)
+    rs = rng.uniform(0.05, 0.15)
+    cs = rng.uniform(0.25, 0.75, size=2)
+    V = rng.uniform(-1.0, 1.0, size=2)
+    phi_s = np.hypot(X - cs[0], Y - cs[1]) - rs
+    XC = cell_coords(nn, h, (0.0, 0.0))
+    mu = 10.0 ** (3.0 * _gauss_field(rng, XC))
+    rho = 0.5 + 1.5 * _gauss_field(rng, XC)
+    u = [rng.normal(0.0, 0.1, size=s) for s in face_shapes(nn)]
+    # prescribed solid velocity: the disc's rigid translation V on faces
+    # within 3h of the disc (its value elsewhere never enters the system)
+    u_bc = []
+    for a in range(2):
+        F = face_coords(nn, h, (0.0, 0.0), a)
+        near = np.hypot(F[0] - cs[0], F[1] - cs[1]) - rs < 3.0 * h
+        u_bc.append(np.where(near, V[a], 0.0))
+    return _case(2, nn, h, (0.0, 0.0), dt, phi_l, phi_s, rho, mu, u, u_bc, g,
+                 name=f"pool2d_{n}", seed=seed, solid_velocity=tuple(V))
+
+
+def config2(seed=2, n=512):
+    c = pool2d(n, seed)
+    c.update(name="config2", tol=1e-6, precision="mixed")
+    return c
+
+
+# --------------------------------------------------------------------------
+# 3D falling column with a perturbed surface (config 3)
+# --------------------------------------------------------------------------
+def column3d(n, seed, dt=1e-3, top=0.8, floor=0.1, radius=0.05, amp=0.01,
+             mu=50.0, rho=1.0, speed=-0.5, g=(0.0, -9.8, 0.0)):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    nn = (n, n, n)
+    X, Y, Z = node_coords(nn, h, (0.0, 0.0, 0.0))
+    m = int(rng.integers(2, 5))
+    lam = rng.uniform(0.1, 0.3)
+    alpha, beta = rng.uniform(0.0, 2.0 * np.pi, size=2)
+    rr = np.hypot(X - 0.5, Z - 0.5)
+    th = np.arctan2(Z - 0.5, X - 0.5)
+    R = radius + amp * np.cos(m * th + alpha) * np.cos(2.0 * np.pi * Y / lam + beta)
+    phi_l = np.maximum(rr - R, Y - top)
+    phi_s = Y - floor
+    u = [np.zeros(s) for s in face_shapes(nn)]
+    u[1][...] = speed
+    return _case(3, nn, h, (0.0, 0.0, 0.0), dt, phi_l, phi_s,
+                 np.full(nn, rho), np.full(nn, mu), u, None, g,
+                 name=f"column3d_{n}", seed=seed)
+
+
+def config3(seed=3, n=128):
+    c = column3d(n, seed)
+    c.update(name="config3", tol=1e-6, precision="mixed")
+    return c
+
+
+# --------------------------------------------------------------------------
+# batched 2D (config 4)
+# --------------------------------------------------------------------------
+def config4_sizes(seed=4, count=64):
+    rng = np.random.default_rng(seed)
+    return [int(v) for v in rng.choice(np.arange(64, 513, 32), size=count)]
+
+
+def config4(seed=4, count=64):
+    sizes = config4_sizes(seed, count)
+    return [dict(drop2d(n, seed * 1000 + q), tol=1e-6, precision="mixed")
+            for q, n in enumerate(sizes)]
+
+
+# --------------------------------------------------------------------------
+# 3D pool with random spheres and a moving sphere (config 5)
+# --------------------------------------------------------------------------
+def pool3d(n, seed, dt=1e-3, n_spheres=8, depth=0.3, g=(0.0, -9.8, 0.0)):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    nn = (n, n, n)
+    X, Y, Z = node_coords(nn, h, (0.0, 0.0, 0.0))
+    phi_l = Y - depth
+    for _ in range(n_spheres):
+        r = rng.uniform(0.05, 0.2)
+        cx, cz = rng.uniform(r, 1.0 - r, size=2)
+        cy = rng.uniform(depth + r, 1.0 - r)
+        phi_l = np.minimum(phi_l, np.sqrt((X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2) - r)
+    del X, Y, Z
+    rs = rng.uniform(0.05, 0.15)
+    cs = rng.uniform(0.25, 0.75, size=3)
+    V = rng.uniform(-1.0, 1.0, size=3)
+    X, Y, Z = node_coords(nn, h, (0.0, 0.0, 0.0))
+    phi_s = np.sqrt((X - cs[0]) ** 2 + (Y - cs[1]) ** 2 + (Z - cs[2]) ** 2) - rs
+    del X, Y, Z
+    XC = cell_coords(nn, h, (0.0, 0.0, 0.0))
+    mu = 10.0 ** (3.0 * _gauss_field(rng, XC))
+    rho = 0.5 + 1.5 * _gauss_field(rng, XC)
+    del XC
+    u = [rng.normal(0.0, 0.1, size=s) for s in face_shapes(nn)]
+    u_bc = []
+    for a in range(3):
+        F = face_coords(nn, h, (0.0, 0.0, 0.0), a)
+        dist = np.sqrt((F[0] - cs[0]) ** 2 + (F[1] - cs[1]) ** 2 + (F[2] - cs[2]) ** 2) - rs
+        del F
+        u_bc.append(np.where(dist < 3.0 * h, V[a], 0.0))
+    return _case(3, nn, h, (0.0, 0.0, 0.0), dt, phi_l, phi_s, rho, mu, u, u_bc, g,
+                 name=f"pool3d_{n}", seed=seed, solid_velocity=tuple(V))
+
+
+def config5(seed=5, n=256):
+    c = pool3d(n, seed)
+    c.update(name="config5", tol=1e-6, precision="mixed")
+    return c
+
+
+def make_config(k, seed=None, **kw):
+    f = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k]
+    return f(**kw) if seed is None else f(seed=seed, **kw)
