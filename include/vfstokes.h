@@ -1,0 +1,190 @@
+/*
+ * vfstokes.h -- C ABI of the MI355X (gfx950) variational Stokes step.
+ *
+ * The library performs one backward-Euler step of time-dependent,
+ * variable-coefficient Stokes flow with free surfaces and (moving) solids,
+ * following "A Simple Finite Difference Method for Time-Dependent, Variable
+ * Coefficient Stokes Flow on Irregular Domains":
+ *   u* = u^n + dt g                         (body force, Section 10)
+ *   volume fractions W_L, W_F               (Section 5, Figs. 3-4)
+ *   null-space elimination                  (Section 7)
+ *   SPD stress/pressure system A x = b      (eq. stokesmixedsystemspd,
+ *                                            factored form of Section 8,
+ *                                            moving-solid RHS of Section 6.2)
+ *   preconditioned CG on A                  (Section 8 end, Section 9)
+ *   velocity recovery from the KKT velocity row (eq. stokesmixedsystem)
+ *
+ * Conventions for every entry point
+ *   - Return value: VFS_OK (0) or a negative VFS_E* code; vfs_last_error()
+ *     gives a message for the last failing call on that context.
+ *   - Pointers passed in may be host or device memory (the library copies
+ *     with hipMemcpyDefault); the caller owns them and may free them after
+ *     the call returns.  The library owns all device memory it allocates.
+ *   - All arrays are FP64, x-fastest (index i + nx_a*(j + ny_a*k)).
+ *       nodes  (level sets):        (nx+1) x (ny+1) [x (nz+1)]
+ *       cells  (rho, mu, p):        nx x ny [x nz]
+ *       u faces: (nx+1) x ny [x nz]; v faces: nx x (ny+1) [x nz];
+ *       w faces: nx x ny x (nz+1)
+ *       2D tau_xy (nodes): (nx+1) x (ny+1)
+ *       3D tau_xy (z-edges): (nx+1)x(ny+1)x nz; tau_xz (y-edges):
+ *          (nx+1) x ny x (nz+1); tau_yz (x-edges): nx x (ny+1) x (nz+1)
+ *   - "Sample order" vectors (vfs_apply, vfs_solve, vfs_get_solution,
+ *     vfs_get_rhs) concatenate, in this order, p, tau_xx, [tau_yy,] tau_xy,
+ *     [tau_xz, tau_yz], each block in its native shape above.  Entries of
+ *     eliminated (inactive) samples are ignored on input and 0 on output.
+ *   - Work is queued on the context's stream; calls that return data to the
+ *     caller synchronise that stream.  A context must not be used from two
+ *     threads at once.
+ */
+#ifndef VFSTOKES_H
+#define VFSTOKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VFS_OK           0
+#define VFS_EINVAL      -1   /* bad argument: NaN/Inf input, rho<=0, mu<=0, dt<=0, sizes */
+#define VFS_ENOMEM      -2   /* device allocation failed */
+#define VFS_EHIP        -3   /* a HIP runtime call failed */
+#define VFS_ENOTCONV    -4   /* max_iter reached; best iterate and velocity still written */
+#define VFS_EBREAKDOWN  -5   /* CG breakdown (p.Ap <= 0 or non-finite); best iterate kept */
+#define VFS_ESTATE      -6   /* call out of order (e.g. solve before assemble) */
+
+/* preconditioners */
+#define VFS_PRECOND_NONE     0
+#define VFS_PRECOND_JACOBI   1   /* diagonal of A */
+#define VFS_PRECOND_LEARNED  3   /* U-Net correction inside flexible CG */
+
+/* arithmetic of the solve */
+#define VFS_FP64   0   /* FP64 vectors, coefficients, apply and reductions */
+#define VFS_MIXED  1   /* FP32 apply/vectors, FP64 reductions, FP64 residual
+                          and iterative-refinement outer steps */
+
+/* sample sets for vfs_get_weights / vfs_get_active */
+#define VFS_SET_CELL    0   /* p, tau_xx, tau_yy */
+#define VFS_SET_FACE_X  1
+#define VFS_SET_FACE_Y  2
+#define VFS_SET_FACE_Z  3
+#define VFS_SET_NODE    4   /* 2D tau_xy */
+#define VFS_SET_EDGE_Z  4   /* 3D tau_xy (same slot as the 2D node set) */
+#define VFS_SET_EDGE_Y  5   /* 3D tau_xz */
+#define VFS_SET_EDGE_X  6   /* 3D tau_yz */
+
+#define VFS_WEIGHT_LIQUID  0  /* W_L */
+#define VFS_WEIGHT_FLUID   1  /* W_F as used by the system (0 on invalid faces) */
+
+typedef struct vfs_ctx vfs_ctx;
+
+typedef struct vfs_stats {
+    int64_t n_samples;        /* candidate unknowns (all tau + p samples) */
+    int64_t n_active;         /* unknowns after null-space elimination */
+    int32_t iterations;       /* total inner CG iterations of the last solve */
+    int32_t outer_iterations; /* refinement steps (mixed) or residual replacements */
+    int32_t status;           /* status of the last solve */
+    int32_t precision;        /* VFS_FP64 / VFS_MIXED */
+    double  rel_residual;     /* FP64 true ||b - A x||_2 / ||b||_2 over active samples */
+    double  b_norm;           /* ||b||_2 */
+    double  t_assemble_ms;    /* (a1)-(a4) of the last step, device time */
+    double  t_solve_ms;       /* first apply to convergence, device time */
+    double  t_recover_ms;     /* velocity recovery, device time */
+    double  t_step_ms;        /* whole step, device time */
+    /* live kernel timing (vfs_set_profiling): average device duration of one
+       launch of the CG apply kernel and of the CG update kernel, from HIP
+       events on the context stream around one launch of each per chunk */
+    double  t_apply_avg_ms;
+    double  t_update_avg_ms;
+    int64_t n_apply_timed;
+    int64_t n_update_timed;
+} vfs_stats;
+
+/* Last error message of a context (or of the failed create when ctx is NULL). */
+const char* vfs_last_error(const vfs_ctx* ctx);
+
+/* Create a context for a dim-D grid (dim 2 or 3) of nx*ny[*nz] cells of size
+ * h whose lower corner is origin[0..dim-1].  nz is ignored in 2D.  The box
+ * walls act as static no-slip solids.  Allocates all device memory for the
+ * grid; *out is NULL on failure. */
+int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const double* origin);
+int vfs_destroy(vfs_ctx* ctx);
+
+/* Queue all work on this hipStream_t (NULL = the null stream). */
+int vfs_set_stream(vfs_ctx* ctx, void* hip_stream);
+
+/* Level sets at grid nodes (phi < 0 inside; phi == 0 counts as outside).
+ * phi_liquid marks the liquid (non-air) region and must be given
+ * everywhere, including inside solids (Fig. 4 caption: the interface is
+ * extrapolated into the solid).  phi_solid may be NULL (no solid besides
+ * the box walls).  Section 5 weights every term by the volume fraction of
+ * its sample's h-sized control volume; the fractions are recomputed from
+ * these level sets by the next assemble/step.  EINVAL on NaN/Inf. */
+int vfs_set_level_sets(vfs_ctx* ctx, const double* phi_liquid, const double* phi_solid);
+
+/* Cell-centred density (> 0) and viscosity (> 0).  Density at a face is
+ * the mean of its in-box cells, viscosity at a node/edge the mean of the
+ * in-box cells sharing it (the diagonal P and M of Section 5). */
+int vfs_set_density(vfs_ctx* ctx, const double* rho_cells);
+int vfs_set_viscosity(vfs_ctx* ctx, const double* mu_cells);
+
+/* Face velocities u^n (w ignored in 2D). */
+int vfs_set_velocity(vfs_ctx* ctx, const double* u, const double* v, const double* w);
+
+/* Prescribed solid velocity u_BC per face (Section 6.2); NULL pointers mean
+ * a static solid.  Values on box faces are ignored (box walls are static). */
+int vfs_set_solid_velocity(vfs_ctx* ctx, const double* ub, const double* vb, const double* wb);
+
+/* Body force per unit mass, g[0..dim-1]. */
+int vfs_set_gravity(vfs_ctx* ctx, const double* g);
+
+/* Solver settings: preconditioner (VFS_PRECOND_*), precision (VFS_FP64 or
+ * VFS_MIXED), relative tolerance on the FP64 true residual ||b-Ax||/||b||
+ * over active samples, iteration cap, and w_min: volume fractions strictly
+ * below w_min are snapped to 0. Defaults: JACOBI, FP64, 1e-6, 100000, 1e-3. */
+int vfs_set_solver(vfs_ctx* ctx, int precond, int precision, double rel_tol,
+                   int max_iter, double w_min);
+
+/* One full step: u* = u + dt g, fractions, coefficients, null-space
+ * elimination, right-hand side, CG solve, velocity recovery.  The new
+ * velocity replaces the context's velocity.  Returns VFS_ENOTCONV /
+ * VFS_EBREAKDOWN with the best iterate applied when the solve fails. */
+int vfs_step(vfs_ctx* ctx, double dt);
+
+/* Steps (a1)-(a4) only: body force, fractions, coefficients, elimination
+ * and right-hand side for this dt (for tests and vfs_apply/vfs_solve). */
+int vfs_assemble(vfs_ctx* ctx, double dt);
+
+/* y = A x on the assembled system (sample order, FP64 path). */
+int vfs_apply(vfs_ctx* ctx, const double* x, double* y);
+
+/* Solve A x = b on the assembled system with the configured solver
+ * (sample order); x is the result, the iterate starts from 0. */
+int vfs_solve(vfs_ctx* ctx, const double* b, double* x);
+
+/* Results of the last step / assemble. */
+int vfs_get_velocity(vfs_ctx* ctx, double* u, double* v, double* w);
+int vfs_get_pressure(vfs_ctx* ctx, double* p);
+/* tau[0..1] (2D: tau_xx, tau_xy) or tau[0..4] (3D: xx, yy, xy, xz, yz) */
+int vfs_get_stress(vfs_ctx* ctx, double* const* tau);
+int vfs_get_solution(vfs_ctx* ctx, double* x);   /* sample order */
+int vfs_get_rhs(vfs_ctx* ctx, double* b);        /* sample order */
+/* W_L or W_F of a sample set (VFS_SET_*), native shape of that set. */
+int vfs_get_weights(vfs_ctx* ctx, int set, int which, double* out);
+/* 1 for active (not eliminated) samples, sample order. */
+int vfs_get_active(vfs_ctx* ctx, uint8_t* out);
+int vfs_get_stats(vfs_ctx* ctx, vfs_stats* out);
+/* Turn live per-kernel timing on (1) or off (0); turning it on resets the
+ * accumulated averages reported in vfs_stats.  Timing adds one event pair
+ * per kernel per chunk of CG iterations. */
+int vfs_set_profiling(vfs_ctx* ctx, int on);
+
+/* Number of entries of a sample-order vector and of the face vector. */
+int vfs_get_sizes(const vfs_ctx* ctx, int64_t* n_samples, int64_t* n_faces);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VFSTOKES_H */

@@ -1,0 +1,402 @@
+// 3D CG kernels on the padded grid, launched over a compacted list of
+// active tiles (64 x 4 anchors in x,y times 8 planes in z).  Tiles without
+// any active sample hold zeros in every solver vector and are skipped.
+//
+// Apply (paper eq. stokesmixedsystemspd, factored form of Section 8):
+// g = K (B x) on faces, y = B^T g + Dg x on samples.  A workgroup marches its
+// 8 z-planes keeping two planes of weighted samples (halo 1 in x,y) and two
+// planes of each face field in LDS, so every face value is formed once and
+// every sample is read once per plane (plus the x,y halo ring).
+//
+// Face rows (numerators; K carries dt/h^2), with X = W tau_xx, Y = W tau_yy,
+// E = W tau_xy (z-edges), F = W tau_xz (y-edges), H = W tau_yz (x-edges):
+//   u(i,j,k): P(i)-P(i-1) + X(i-1)-X(i) + E(i,j,k)-E(i,j+1,k) + F(i,j,k)-F(i,j,k+1)
+//   v(i,j,k): P(j)-P(j-1) + Y(j-1)-Y(j) + E(i,j,k)-E(i+1,j,k) + H(i,j,k)-H(i,j,k+1)
+//   w(i,j,k): P(k)-P(k-1) + X(k)-X(k-1) + Y(k)-Y(k-1) + F(i,j,k)-F(i+1,j,k)
+//             + H(i,j,k)-H(i,j+1,k)
+#include "vfs_internal.h"
+#include "vfs_reduce.h"
+
+namespace vfs {
+namespace {
+
+constexpr int TX = 64, TY = 4, KZ = 8, NT = 256;
+constexpr int HX = TX + 2, HY = TY + 2;
+constexpr int FX = TX + 1, FY = TY + 1;
+
+__device__ __forceinline__ void tile_origin(const Tiles& t, int& i0, int& j0, int& k0) {
+    const int id = t.list[blockIdx.x];
+    const int tx = id % t.ntx;
+    const int ty = (id / t.ntx) % t.nty;
+    const int tz = id / (t.ntx * t.nty);
+    i0 = tx * TX;
+    j0 = ty * TY;
+    k0 = tz * KZ;
+}
+
+template <typename T, int MODE, bool ZIN>
+struct Loader {
+    const Geo& g;
+    const T* r;
+    const T* zs;
+    const T* dinv;
+    const T* pin;
+    T* pout;
+    const T* a;
+    T beta;
+    bool first;
+
+    // value of slice s at offset os (direction update in MODE_DIR)
+    __device__ __forceinline__ T value(long long os, bool own) const {
+        if (MODE == MODE_DIR) {
+            const T z = ZIN ? zs[os] : dinv[os] * r[os];
+            const T val = first ? z : z + beta * pin[os];
+            if (own) pout[os] = val;
+            return val;
+        }
+        return pin[os];
+    }
+};
+
+template <typename T, int MODE, bool ZIN>
+__global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __restrict__ r,
+                                                const T* __restrict__ zs,
+                                                const T* __restrict__ dinv,
+                                                const T* __restrict__ pin, T* __restrict__ pout,
+                                                T* __restrict__ q, const T* __restrict__ a,
+                                                const T* __restrict__ c, const T* __restrict__ K,
+                                                const T* __restrict__ bv, RedArgs ra) {
+    T beta = T(0);
+    bool first = true;
+    if (MODE == MODE_DIR) {
+        if (ra.sc->done) return;
+        double bd;
+        if (!cg_direction_preamble<NT>(ra, blockIdx.x, bd)) return;
+        first = ra.kidx == 0;
+        beta = (T)bd;
+    }
+    __shared__ T sW[2][6][HY][HX];
+    __shared__ T gU[2][FY][FX];
+    __shared__ T gV[2][FY][FX];
+    __shared__ T gW[2][FY][FX];
+    const long long NP = g.NP;
+    int i0, j0, k0;
+    tile_origin(tl, i0, j0, k0);
+    const int kend = min(k0 + KZ, g.nz + 1);
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    Loader<T, MODE, ZIN> ld{g, r, zs, dinv, pin, pout, a, beta, first};
+
+    T vcur[6], acur[6], vnext[6], anext[6];
+
+    // load weighted plane kk into ring slot kk&1; own anchor values -> vo, ao
+    auto load_plane = [&](int kk, T (&vo)[6], T (&ao)[6]) {
+        const int sl = kk & 1;
+        {   // own interior anchor
+            const int i = i0 + tx, j = j0 + ty;
+            const bool in = i <= g.nx + 1 && j <= g.ny + 1 && kk <= g.nz + 1;
+            const bool own = in && i <= g.nx && j <= g.ny && kk >= k0 && kk < kend;
+            const long long o = in ? g.idx(i, j, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                T val = T(0), aw = T(0);
+                if (in) {
+                    const long long os = o + s * NP;
+                    val = ld.value(os, own);
+                    aw = a[os];
+                }
+                vo[s] = val;
+                ao[s] = aw;
+                sW[sl][s][ty + 1][tx + 1] = aw * val;
+            }
+        }
+        // halo ring: rows lj = 0 and HY-1 (HX each), columns li = 0 and HX-1 (TY each)
+        if (tid < 2 * HX + 2 * TY) {
+            int li, lj;
+            if (tid < HX) {
+                li = tid;
+                lj = 0;
+            } else if (tid < 2 * HX) {
+                li = tid - HX;
+                lj = HY - 1;
+            } else {
+                const int e = tid - 2 * HX;
+                lj = 1 + (e >> 1);
+                li = (e & 1) ? HX - 1 : 0;
+            }
+            const int i = i0 - 1 + li, j = j0 - 1 + lj;
+            const bool in = i <= g.nx + 1 && j <= g.ny + 1 && kk <= g.nz + 1;
+            const long long o = in ? g.idx(i, j, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                T w = T(0);
+                if (in) {
+                    const long long os = o + s * NP;
+                    w = a[os] * ld.value(os, false);
+                }
+                sW[sl][s][lj][li] = w;
+            }
+        }
+    };
+
+    // faces: g_u(kk), g_v(kk) from planes kk, kk+1; g_w(kk+1) from planes kk, kk+1
+    auto faces = [&](int kk, bool uv, bool w) {
+        const int s0 = kk & 1, s1 = (kk + 1) & 1;
+        for (int e = tid; e < FX * FY; e += NT) {
+            const int li = e % FX, lj = e / FX;
+            if (uv) {
+                {   // u face (i0+li, j0-1+lj, kk): weighted indices li (i-1), li+1 (i), lj+...
+                    const int i = i0 + li, j = j0 - 1 + lj;
+                    T gv = T(0);
+                    if (i <= g.nx && j >= 0 && j < g.ny && kk >= 0 && kk < g.nz) {
+                        const T kf = K[g.idx(i, j, kk)];
+                        // P,X at (i-1): [lj][li], (i): [lj][li+1]; E at j: [lj][li+1], j+1: [lj+1][li+1]
+                        const T d = (sW[s0][0][lj][li + 1] - sW[s0][0][lj][li]) +
+                                    (sW[s0][1][lj][li] - sW[s0][1][lj][li + 1]) +
+                                    (sW[s0][3][lj][li + 1] - sW[s0][3][lj + 1][li + 1]) +
+                                    (sW[s0][4][lj][li + 1] - sW[s1][4][lj][li + 1]);
+                        gv = kf * d;
+                    }
+                    gU[s0][lj][li] = gv;
+                }
+                {   // v face (i0-1+li, j0+lj, kk)
+                    const int i = i0 - 1 + li, j = j0 + lj;
+                    T gv = T(0);
+                    if (i >= 0 && i < g.nx && j <= g.ny && kk >= 0 && kk < g.nz) {
+                        const T kf = K[NP + g.idx(i, j, kk)];
+                        // weighted (i): li, (i+1): li+1; (j): lj+1, (j-1): lj
+                        const T d = (sW[s0][0][lj + 1][li] - sW[s0][0][lj][li]) +
+                                    (sW[s0][2][lj][li] - sW[s0][2][lj + 1][li]) +
+                                    (sW[s0][3][lj + 1][li] - sW[s0][3][lj + 1][li + 1]) +
+                                    (sW[s0][5][lj + 1][li] - sW[s1][5][lj + 1][li]);
+                        gv = kf * d;
+                    }
+                    gV[s0][lj][li] = gv;
+                }
+            }
+            if (w) {   // w face (i0-1+li, j0-1+lj, kk+1): weighted (i): li, (j): lj
+                const int i = i0 - 1 + li, j = j0 - 1 + lj, kw = kk + 1;
+                T gv = T(0);
+                if (i >= 0 && i < g.nx && j >= 0 && j < g.ny && kw >= 0 && kw <= g.nz) {
+                    const T kf = K[2 * NP + g.idx(i, j, kw)];
+                    const T d = (sW[s1][0][lj][li] - sW[s0][0][lj][li]) +
+                                (sW[s1][1][lj][li] - sW[s0][1][lj][li]) +
+                                (sW[s1][2][lj][li] - sW[s0][2][lj][li]) +
+                                (sW[s1][4][lj][li] - sW[s1][4][lj][li + 1]) +
+                                (sW[s1][5][lj][li] - sW[s1][5][lj + 1][li]);
+                    gv = kf * d;
+                }
+                gW[s1][lj][li] = gv;
+            }
+        }
+    };
+
+    // prologue: planes k0-1 and k0, faces u,v at k0-1 and w at k0
+    load_plane(k0 - 1, vnext, anext);
+    load_plane(k0, vcur, acur);
+    __syncthreads();
+    faces(k0 - 1, true, true);
+    __syncthreads();
+
+    double acc = 0.0;
+    for (int k = k0; k < kend; ++k) {
+        load_plane(k + 1, vnext, anext);
+        __syncthreads();
+        faces(k, true, true);
+        __syncthreads();
+        const int i = i0 + tx, j = j0 + ty;
+        if (i <= g.nx && j <= g.ny) {
+            const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;
+            const T gu0 = gU[sk][ty + 1][tx], gu1 = gU[sk][ty + 1][tx + 1];
+            const T gum = gU[sk][ty][tx], guz = gU[sp][ty + 1][tx];
+            const T gv0 = gV[sk][ty][tx + 1], gv1 = gV[sk][ty + 1][tx + 1];
+            const T gvm = gV[sk][ty][tx], gvz = gV[sp][ty][tx + 1];
+            const T gw0 = gW[sk][ty + 1][tx + 1], gw1 = gW[sn][ty + 1][tx + 1];
+            const T gwx = gW[sk][ty + 1][tx], gwy = gW[sk][ty][tx + 1];
+            const long long o = g.idx(i, j, k);
+            const T c1 = c[NP + o], c2 = c[2 * NP + o];
+            const T cross = T(0.5) * fmin(c1, c2);
+            T y[6];
+            y[0] = acur[0] * ((gu0 - gu1) + (gv0 - gv1) + (gw0 - gw1));
+            y[1] = acur[1] * ((gu1 - gu0) + (gw0 - gw1)) + c1 * vcur[1] + cross * vcur[2];
+            y[2] = acur[2] * ((gv1 - gv0) + (gw0 - gw1)) + c2 * vcur[2] + cross * vcur[1];
+            y[3] = acur[3] * ((gu0 - gum) + (gv0 - gvm)) + c[3 * NP + o] * vcur[3];
+            y[4] = acur[4] * ((gu0 - guz) + (gw0 - gwx)) + c[4 * NP + o] * vcur[4];
+            y[5] = acur[5] * ((gv0 - gvz) + (gw0 - gwy)) + c[5 * NP + o] * vcur[5];
+            if (MODE == MODE_RESID) {
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    const T rr = bv[s * NP + o] - y[s];
+                    q[s * NP + o] = rr;
+                    acc += (double)rr * (double)rr;
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    q[s * NP + o] = y[s];
+                    if (MODE == MODE_DIR) acc += (double)vcur[s] * (double)y[s];
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            vcur[s] = vnext[s];
+            acur[s] = anext[s];
+        }
+    }
+    if (MODE == MODE_APPLY) return;
+    double vv[1] = {acc};
+    block_partial<1, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
+}
+
+// x += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r over the active tiles
+template <typename T>
+__global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict__ x,
+                                                 const T* __restrict__ p, T* __restrict__ r,
+                                                 const T* __restrict__ q,
+                                                 const T* __restrict__ dinv, T* __restrict__ z,
+                                                 RedArgs ra) {
+    Scalars* sc = ra.sc;
+    if (sc->done) return;
+    double tot[1];
+    reduce_partials<1, NT>(ra.part_in, ra.nb_in, tot);
+    const double pq = tot[0];
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->done = 3;
+            sc->iter = ra.kidx;
+        }
+        return;
+    }
+    const double alpha_d = sc->rz[ra.kidx & 1] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha_d;
+    }
+    const T alpha = (T)alpha_d;
+    const long long NP = g.NP;
+    int i0, j0, k0;
+    tile_origin(tl, i0, j0, k0);
+    const int kend = min(k0 + KZ, g.nz + 1);
+    const int i = i0 + (threadIdx.x & 63), j = j0 + (threadIdx.x >> 6);
+    double rz = 0.0, rr = 0.0;
+    if (i <= g.nx && j <= g.ny) {
+        for (int k = k0; k < kend; ++k) {
+            const long long o = g.idx(i, j, k);
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const long long t = o + s * NP;
+                const T ri = r[t] - alpha * q[t];
+                const T zi = dinv[t] * ri;
+                x[t] = x[t] + alpha * p[t];
+                r[t] = ri;
+                if (z) z[t] = zi;
+                rz += (double)ri * (double)zi;
+                rr += (double)ri * (double)ri;
+            }
+        }
+    }
+    double vv[2] = {rz, rr};
+    block_partial<2, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
+}
+
+// tile t is active if any sample anchored in it has a != 0
+__global__ __launch_bounds__(NT) void k_tile_flags(Geo g, int ntx, int nty, int ntz,
+                                                   const double* __restrict__ a,
+                                                   int* __restrict__ flags) {
+    const int id = blockIdx.x;
+    const int tx = id % ntx, ty = (id / ntx) % nty, tz = id / (ntx * nty);
+    const int i = tx * TX + (threadIdx.x & 63), j = ty * TY + (threadIdx.x >> 6);
+    const int k0 = tz * KZ, kend = min(k0 + KZ, g.nz + 1);
+    int any = 0;
+    if (i <= g.nx && j <= g.ny)
+        for (int k = k0; k < kend; ++k)
+            for (int s = 0; s < 6; ++s) any |= a[s * g.NP + g.idx(i, j, k)] != 0.0;
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) flags[id] = any ? 1 : 0;
+}
+
+// ordered compaction of the active tile ids (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void k_tile_compact(int n, const int* __restrict__ flags,
+                                                       int* __restrict__ list,
+                                                       int* __restrict__ count) {
+    __shared__ int s_cnt[1024];
+    const int per = (n + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    int c = 0;
+    for (int t = lo; t < hi; ++t) c += flags[t];
+    s_cnt[threadIdx.x] = c;
+    __syncthreads();
+    // sequential-in-thread-0 exclusive scan is enough for 1024 entries
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int q = 0; q < 1024; ++q) {
+            const int v = s_cnt[q];
+            s_cnt[q] = run;
+            run += v;
+        }
+        *count = run;
+    }
+    __syncthreads();
+    int w = s_cnt[threadIdx.x];
+    for (int t = lo; t < hi; ++t)
+        if (flags[t]) list[w++] = t;
+}
+
+}  // namespace
+
+void tile_dims(const Geo& g, int& ntx, int& nty, int& ntz) {
+    ntx = (g.nx + 1 + TX - 1) / TX;
+    nty = (g.ny + 1 + TY - 1) / TY;
+    ntz = (g.nz + 1 + KZ - 1) / KZ;
+}
+
+void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* count,
+                  hipStream_t s) {
+    int ntx, nty, ntz;
+    tile_dims(g, ntx, nty, ntz);
+    const int n = ntx * nty * ntz;
+    hipLaunchKernelGGL(k_tile_flags, dim3(n), dim3(NT), 0, s, g, ntx, nty, ntz, a, flags);
+    hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, n, flags, list, count);
+}
+
+template <typename T>
+void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,
+                    const T* dinv, const T* pin, T* pout, T* q, const T* a, const T* c,
+                    const T* K, const T* bvec, const RedArgs& ra, hipStream_t s) {
+    if (tl.count <= 0) return;
+    const dim3 gs(tl.count);
+    if (mode == MODE_DIR) {
+        if (zin)
+            hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
+                               dinv, pin, pout, q, a, c, K, bvec, ra);
+        else
+            hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
+                               dinv, pin, pout, q, a, c, K, bvec, ra);
+    } else if (mode == MODE_APPLY) {
+        hipLaunchKernelGGL((k_apply3d<T, MODE_APPLY, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
+                           dinv, pin, pout, q, a, c, K, bvec, ra);
+    } else {
+        hipLaunchKernelGGL((k_apply3d<T, MODE_RESID, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
+                           dinv, pin, pout, q, a, c, K, bvec, ra);
+    }
+}
+
+template <typename T>
+void launch_update3d(const Geo& g, const Tiles& tl, T* x, const T* p, T* r, const T* q,
+                     const T* dinv, T* z, const RedArgs& ra, hipStream_t s) {
+    if (tl.count <= 0) return;
+    hipLaunchKernelGGL((k_update3d<T>), dim3(tl.count), dim3(NT), 0, s, g, tl, x, p, r, q, dinv, z,
+                       ra);
+}
+
+#define VFS_INST3(T)                                                                           \
+    template void launch_apply3d<T>(const Geo&, const Tiles&, int, bool, const T*, const T*,   \
+                                    const T*, const T*, T*, T*, const T*, const T*, const T*,   \
+                                    const T*, const RedArgs&, hipStream_t);                    \
+    template void launch_update3d<T>(const Geo&, const Tiles&, T*, const T*, T*, const T*,      \
+                                     const T*, T*, const RedArgs&, hipStream_t);
+VFS_INST3(double)
+VFS_INST3(float)
+
+}  // namespace vfs

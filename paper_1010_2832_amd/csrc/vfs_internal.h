@@ -1,0 +1,271 @@
+// Internal declarations of the vfstokes HIP library (gfx950).
+//
+// Device data layout ("padded grid"): every per-sample array of every type
+// (cells, faces, nodes/edges) lives on the same padded 2D/3D array so that a
+// thread anchored at logical index (i,j[,k]) finds every sample type anchored
+// there at the same offset:
+//   offset(i,j)   = FRONT + (j+1)*PX + i                   (2D)
+//   offset(i,j,k) = FRONT + ((k+1)*PY + (j+1))*PX + i      (3D)
+// PX >= nx+3 is rounded up to a multiple of 16 elements, PY = ny+3, PZ = nz+3.
+// The ghost index -1 along x is the last (always zero) padding element of the
+// previous row; along y/z it is a zero row/plane; FRONT (16 elements) holds
+// the ghost of the very first row.  Elements outside a sample type's valid
+// range stay zero for the lifetime of the array, so stencils never need a
+// bounds test for reads at distance one.
+//
+// A multi-component quantity (all stress/pressure samples, all faces) is one
+// allocation of S slices of NP elements; slice s starts at s*NP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/vfstokes.h"
+
+namespace vfs {
+
+constexpr int kFront = 16;
+
+struct Geo {
+    int dim;
+    int nx, ny, nz;          // cells (nz = 1 in 2D)
+    int PX, PY, PZ;          // padded extents (PZ = 1 in 2D)
+    long long NP;            // elements of one padded array (incl. front/tail pads)
+    double h;
+
+    __host__ __device__ inline long long idx(int i, int j) const {
+        return (long long)kFront + (long long)(j + 1) * PX + i;
+    }
+    __host__ __device__ inline long long idx(int i, int j, int k) const {
+        return (long long)kFront + ((long long)(k + 1) * PY + (j + 1)) * PX + i;
+    }
+    // number of stress+pressure sample types and face types
+    __host__ __device__ inline int nsamp() const { return dim == 2 ? 3 : 6; }
+    __host__ __device__ inline int nface() const { return dim; }
+    // number of weight sets: 2D cell,u,v,node; 3D cell,u,v,w,ez,ey,ex
+    __host__ __device__ inline int nsets() const { return dim == 2 ? 4 : 7; }
+};
+
+Geo make_geo(int dim, int nx, int ny, int nz, double h);
+
+// stagger of weight set s (1 = cell-centred along that axis): used for
+// shapes of user-facing arrays.
+void set_stagger(int dim, int set, int st[3]);
+// weight set of sample slice s (p, txx, [tyy], txy, [txz, tyz])
+int sample_set(int dim, int s);
+// compact shape of a set
+void set_shape(const Geo& g, int set, int shp[3]);
+
+// Device scalars of one CG solve.  Written only by workgroup 0 of a kernel
+// and read only by later kernels (r.z is double-buffered by iteration
+// parity so that the kernel writing iteration k's value never overwrites the
+// value of iteration k-1 that its other workgroups still read).
+struct Scalars {
+    double rz[2];       // r.z of iteration k in slot k&1
+    double rr;          // r.r of the last checked iterate
+    double bb;          // b.b of the system being solved
+    double tol2;        // stop when rr <= tol2 * bb
+    double pq;          // p.Ap of the last iteration
+    double alpha, beta;
+    double aux0, aux1;  // finalized norms (residual checks)
+    double rz_prev_z;   // flexible CG: r_{k}.z_{k-1}
+    int iter;           // iterations completed when done was set
+    int max_iter;
+    int done;           // 0 running, 1 converged, 2 max_iter, 3 breakdown
+    int flexible;
+    long long n_active;
+    int pad[4];
+};
+
+// Partial-sum plumbing of one reduction-carrying launch.
+struct RedArgs {
+    Scalars* sc;
+    const double* part_in;   // partials of the previous kernel
+    int nb_in;               // how many workgroups wrote them
+    double* part_out;        // this kernel's partials (one per workgroup)
+    int kidx;                // CG iteration index within the current run
+    int set_bb;              // first iteration of a fresh solve: bb := r.r
+};
+
+// Compacted list of active 3D tiles (64 x 4 anchors in x,y times 8 planes
+// in z); unused in 2D.
+struct Tiles {
+    const int* list;
+    int count;
+    int ntx, nty, ntz;
+};
+
+}  // namespace vfs
+
+struct vfs_ctx {
+    vfs::Geo g;
+    hipStream_t stream = nullptr;
+    std::string err;
+    double origin[3] = {0, 0, 0};
+
+    // settings
+    int precond = VFS_PRECOND_JACOBI;
+    int precision = VFS_FP64;
+    double tol = 1e-6;
+    int max_iter = 100000;
+    double w_min = 1e-3;
+    double gravity[3] = {0, 0, 0};
+
+    // inputs (device)
+    double* phi_l = nullptr;     // compact nodal
+    double* phi_s = nullptr;     // compact nodal (valid if has_solid)
+    bool has_solid = false;
+    bool have_phi = false, have_rho = false, have_mu = false, have_u = false;
+    double* rho = nullptr;       // padded cells
+    double* mu = nullptr;        // padded cells
+    double* u = nullptr;         // padded faces, dim slices (u^n, then u^{n+1})
+    double* ubc = nullptr;       // padded faces, dim slices
+
+    // assembly (device)
+    double* thL = nullptr;       // compact sub-cell liquid fractions (2n)^d
+    double* thF = nullptr;       // compact sub-cell fluid fractions
+    double* WL = nullptr;        // padded, nsets slices
+    double* WF = nullptr;        // padded, nsets slices (faces: after invalidation)
+    uint8_t* fflag = nullptr;    // padded faces, dim slices: bit0 K>0, bit1 bad, bit2 invalid
+    double* ustar = nullptr;     // padded faces
+    double* rhof = nullptr;      // padded faces
+    double* K = nullptr;         // padded faces: dt/h^2 * W_F / (rho W_L)
+    double* a = nullptr;         // padded samples: W_L * active
+    double* c = nullptr;         // padded samples: W_F W_L / mu * active (stresses)
+    double* dinv = nullptr;      // padded samples: 1 / diag(A) (0 inactive)
+    double* b = nullptr;         // padded samples
+    float* K32 = nullptr;
+    float* a32 = nullptr;
+    float* c32 = nullptr;
+    float* dinv32 = nullptr;
+
+    // solver vectors (padded samples)
+    double* x = nullptr;
+    double* r = nullptr;
+    double* p0 = nullptr;
+    double* p1 = nullptr;
+    double* q = nullptr;
+    double* z = nullptr;
+    float* x32 = nullptr;
+    float* r32 = nullptr;
+    float* p032 = nullptr;
+    float* p132 = nullptr;
+    float* q32 = nullptr;
+    float* z32 = nullptr;
+
+    // reductions
+    double* partials = nullptr;  // per-workgroup partial sums: regions A, B, R
+    long long capA = 0, capB = 0;
+    unsigned* counter = nullptr;
+    vfs::Scalars* sc = nullptr;      // device
+    vfs::Scalars* sc_host = nullptr; // pinned mirror
+    int* flag = nullptr;             // device: input validation flag
+    int* flag_host = nullptr;        // pinned
+
+    // staging for user copies (device, compact)
+    double* stage = nullptr;
+    long long stage_elems = 0;
+
+    // active tiles (3D)
+    int* tile_flags = nullptr;
+    int* tile_list = nullptr;
+    int* tile_count = nullptr;
+    int* tile_count_host = nullptr;  // pinned
+    vfs::Tiles tiles{nullptr, 0, 0, 0, 0};
+
+    bool assembled = false;
+    double dt_assembled = 0.0;
+    vfs_stats stats{};
+    hipEvent_t ev[6] = {};
+    bool prof = false;
+    hipEvent_t pev[4] = {};
+    double prof_apply_ms = 0.0, prof_update_ms = 0.0;
+    long long prof_apply_n = 0, prof_update_n = 0;
+};
+
+namespace vfs {
+
+// ---- launchers (defined in the .hip files) ----
+// fractions / weights (k_fractions.hip)
+void launch_subcell_fractions(const Geo& g, const double* phi, double* theta, bool complement,
+                              hipStream_t s);
+void launch_fill(double* dst, long long n, double v, hipStream_t s);
+void launch_weights(const Geo& g, const double* thL, const double* thF, double w_min,
+                    double* WL, double* WF, hipStream_t s);
+// 2D assembly (k_assemble2d.hip)
+void launch_face_coef2d(const Geo& g, double dt, const double* g3, const double* WL, double* WF,
+                        const double* rho, const double* u, double* ustar, double* rhof,
+                        double* K, uint8_t* fflag, hipStream_t s);
+void launch_sample_coef2d(const Geo& g, const double* WL, const double* WF, const double* mu,
+                          const double* K, const uint8_t* fflag, const double* ustar,
+                          const double* ubc, double* a, double* c, double* dinv, double* b,
+                          Scalars* sc, hipStream_t s);
+void launch_velocity2d(const Geo& g, double dt, const double* x, const double* a,
+                       const double* ustar, const double* ubc, const double* rhof,
+                       const double* WL, const double* WF, const uint8_t* fflag, double* u,
+                       hipStream_t s);
+// 3D assembly (k_assemble3d.hip)
+void launch_face_coef3d(const Geo& g, double dt, const double* g3, const double* WL, double* WF,
+                        const double* rho, const double* u, double* ustar, double* rhof,
+                        double* K, uint8_t* fflag, hipStream_t s);
+void launch_sample_coef3d(const Geo& g, const double* WL, const double* WF, const double* mu,
+                          const double* K, const uint8_t* fflag, const double* ustar,
+                          const double* ubc, double* a, double* c, double* dinv, double* b,
+                          Scalars* sc, hipStream_t s);
+void launch_velocity3d(const Geo& g, double dt, const double* x, const double* a,
+                       const double* ustar, const double* ubc, const double* rhof,
+                       const double* WL, const double* WF, const uint8_t* fflag, double* u,
+                       hipStream_t s);
+
+// packing and checks (k_util.hip)
+void launch_pack(const Geo& g, const int shp[3], const double* src, double* dst, hipStream_t s);
+void launch_unpack(const Geo& g, const int shp[3], const double* src, double* dst, hipStream_t s);
+void launch_unpack_active(const Geo& g, const int shp[3], const double* a, uint8_t* dst,
+                          hipStream_t s);
+void launch_check(const double* v, long long n, int positive, int* flag, hipStream_t s);
+void launch_zero_box_faces(const Geo& g, double* faces, hipStream_t s);
+void launch_to_f32(const double* src, float* dst, long long n, hipStream_t s);
+void launch_mask(double* dst, const double* src, const double* a, long long n, hipStream_t s);
+
+// CG building blocks (k_pcg.hip); T = double or float
+enum ApplyMode { MODE_DIR = 0, MODE_APPLY = 1, MODE_RESID = 2 };
+int apply_grid_blocks(const Geo& g);   // 2D apply grid / all 3D tiles (capacity)
+int vec_grid_blocks(const Geo& g);     // dense pointwise kernels
+// workgroups of one apply / update launch (the partial count they write)
+int apply_blocks(const Geo& g, const Tiles& tl);
+int update_blocks(const Geo& g, const Tiles& tl);
+template <typename T>
+void launch_apply(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,
+                  const T* dinv, const T* pin, T* pout, T* q, const T* a, const T* c, const T* K,
+                  const T* bvec, const RedArgs& ra, hipStream_t s);
+template <typename T>
+void launch_update(const Geo& g, const Tiles& tl, T* x, const T* p, T* r, const T* q,
+                   const T* dinv, T* z, const RedArgs& ra, hipStream_t s);
+template <typename T>
+void launch_cg_restart(const Geo& g, const T* r, const T* dinv, T* z, Scalars* sc,
+                       double* part_out, int max_iter, hipStream_t s);
+template <typename T>
+void launch_cg_init(const Geo& g, const T* bsrc, T* x, T* r, const T* dinv, T* z, double tol,
+                    int max_iter, Scalars* sc, double* part_out, hipStream_t s);
+// one workgroup sums nb partials (nv values each) into sc->aux0 (slot 0) / aux1
+void launch_finalize(const double* part, int nb, int nv, Scalars* sc, int slot, hipStream_t s);
+// mixed precision glue
+void launch_scale_to_f32(const Geo& g, const double* r64, float* r32, const Scalars* sc,
+                         hipStream_t s);
+void launch_axpy_f32_to_f64(const Geo& g, double* x64, const float* d32, const Scalars* sc,
+                            hipStream_t s);
+void launch_norm2(const Geo& g, const double* v, double* part_out, hipStream_t s);
+// 3D tiles (k_apply3d.hip)
+void tile_dims(const Geo& g, int& ntx, int& nty, int& ntz);
+void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* count,
+                  hipStream_t s);
+template <typename T>
+void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,
+                    const T* dinv, const T* pin, T* pout, T* q, const T* a, const T* c,
+                    const T* K, const T* bvec, const RedArgs& ra, hipStream_t s);
+template <typename T>
+void launch_update3d(const Geo& g, const Tiles& tl, T* x, const T* p, T* r, const T* q,
+                     const T* dinv, T* z, const RedArgs& ra, hipStream_t s);
+
+}  // namespace vfs

@@ -1,0 +1,104 @@
+// Deterministic FP64 reductions across workgroups without atomics or fences.
+//
+// A producer kernel writes one partial sum per workgroup (plain stores).  The
+// consumer is the *next* kernel on the stream: the kernel boundary makes the
+// partials visible, and every consumer workgroup sums all partials itself in
+// a fixed order (strided per thread, wave-xor tree, waves in order), so every
+// workgroup obtains bit-identical totals and may act on them uniformly.
+// This avoids the device-scope release/acquire of a "last workgroup" scheme,
+// which on a multi-XCD part writes back the whole L2 per workgroup.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "vfs_internal.h"
+
+namespace vfs {
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Writes this workgroup's sums of v[] to part[q * nb + bid].
+template <int NV, int NT>
+__device__ __forceinline__ void block_partial(double (&v)[NV], double* __restrict__ part, int nb,
+                                              int bid) {
+    constexpr int NW = NT / 64;
+    __shared__ double sw[NV][NW];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = wave_sum64(v[q]);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sw[q][wid] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = sw[q][0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) s += sw[q][w];
+            part[(long long)q * nb + bid] = s;
+        }
+    }
+}
+
+// Every thread of the workgroup receives the totals of part[q * nb + 0..nb).
+template <int NV, int NT>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb,
+                                                double (&tot)[NV]) {
+    constexpr int NW = NT / 64;
+    __shared__ double sr[NV][NW];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += NT) s += part[(long long)q * nb + b];
+        s = wave_sum64(s);
+        if (lane == 0) sr[q][wid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = sr[q][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s += sr[q][w];
+        tot[q] = s;
+    }
+    __syncthreads();
+}
+
+// Shared preamble of a MODE_DIR apply: returns false if the solve stops here
+// (converged, iteration cap, non-finite); sets beta.
+template <int NT>
+__device__ __forceinline__ bool cg_direction_preamble(const RedArgs& ra, int bid, double& beta) {
+    Scalars* sc = ra.sc;
+    double tot[2];
+    reduce_partials<2, NT>(ra.part_in, ra.nb_in, tot);
+    const double rzk = tot[0], rrk = tot[1];
+    const double bb = ra.set_bb ? rrk : sc->bb;
+    int stop = 0;
+    if (!isfinite(rzk) || !isfinite(rrk))
+        stop = 3;
+    else if (rrk <= sc->tol2 * bb)
+        stop = 1;
+    else if (ra.kidx >= sc->max_iter)
+        stop = 2;
+    beta = ra.kidx == 0 ? 0.0 : rzk / sc->rz[(ra.kidx + 1) & 1];
+    if (bid == 0 && threadIdx.x == 0) {
+        sc->rz[ra.kidx & 1] = rzk;
+        sc->rr = rrk;
+        sc->beta = beta;
+        if (ra.set_bb) sc->bb = bb;
+        if (stop) {
+            sc->done = stop;
+            sc->iter = ra.kidx;
+        }
+    }
+    return stop == 0;
+}
+
+}  // namespace vfs

@@ -1,0 +1,31 @@
+"""Helpers shared by the GPU parity tests: run a case through the C ABI and
+compare with the oracle."""
+import numpy as np
+
+from oracle import system
+
+
+def gpu_run(case, precision=0, tol=None, step=True, max_iter=200000, w_min=1e-3):
+    from paper_1010_2832_amd import vfstokes as V
+    ctx = V.context_from_case(case, precision=precision, tol=tol, max_iter=max_iter, w_min=w_min)
+    if step:
+        ctx.vfs_step(case["dt"])
+    else:
+        ctx.vfs_assemble(case["dt"])
+    return ctx
+
+
+def flat_faces(grid, comps):
+    return np.concatenate([grid.flat(q) for q in comps])
+
+
+def velocity_rel_linf(asm, u_gpu_flat, u_ref_flat):
+    m = asm.K > 0
+    if not m.any():
+        return 0.0
+    scale = max(np.abs(u_ref_flat[m]).max(), 1e-300)
+    return np.abs(u_gpu_flat[m] - u_ref_flat[m]).max() / scale
+
+
+def oracle(case, w_min=1e-3):
+    return system.step(case, w_min=w_min)

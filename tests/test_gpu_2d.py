@@ -1,0 +1,220 @@
+"""GPU parity of the 2D path against the oracle (through the C ABI).
+
+Integer work (weights that decide classification, active masks) must match
+bit for bit; floating-point results within the stated tolerances:
+apply and right-hand side to 1e-12 relative, velocity relative L-inf 1e-6
+(FP64 path) and 1e-4 (mixed path)."""
+import numpy as np
+import pytest
+
+import analytic
+import cases
+from gpu_util import flat_faces, gpu_run, oracle, velocity_rel_linf
+from oracle import system
+
+pytestmark = pytest.mark.gpu
+
+
+def _banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+def _ragged_case(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / max(nx, ny)
+    nn = (nx, ny)
+    X = cases.node_coords(nn, h, (0.0, 0.0))
+    phi_l = np.minimum(np.hypot(X[0] - 0.45 * nx * h, X[1] - 0.55 * ny * h) - 0.3 * min(nx, ny) * h,
+                       X[1] - 0.25 * ny * h)
+    phi_s = np.hypot(X[0] - 0.6 * nx * h, X[1] - 0.2 * ny * h) - 0.12 * min(nx, ny) * h
+    u = [rng.normal(0, 0.2, size=s) for s in cases.face_shapes(nn)]
+    ubc = [np.full(s, 0.3 * (a + 1)) for a, s in enumerate(cases.face_shapes(nn))]
+    return dict(dim=2, n=nn, h=h, origin=(0.0, 0.0), dt=0.02, phi_l=phi_l, phi_s=phi_s,
+                rho=rng.uniform(0.5, 2.0, size=nn), mu=rng.uniform(0.5, 5.0, size=nn),
+                u=u, u_bc=ubc, g=(0.0, -1.0), name=f"ragged{nx}x{ny}")
+
+
+CASES = {
+    "config1": lambda: cases.config1(),
+    "ragged37x53": lambda: _ragged_case(37, 53, 1),
+    "ragged130x67": lambda: _ragged_case(130, 67, 2),
+    "E2_64": lambda: analytic.make_case("E2", 64),
+    "E4_64": lambda: analytic.make_case("E4", 64),
+    "E5_64": lambda: analytic.make_case("E5", 64),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_weights_and_masks_bitexact(name):
+    from paper_1010_2832_amd import vfstokes as V
+    _banner(f"weights/masks {name}")
+    case = CASES[name]()
+    asm = system.assemble(case)
+    ctx = gpu_run(case, step=False)
+    g = asm.grid
+    sets = {V.VFS_SET_CELL: g.cell, V.VFS_SET_FACE_X: g.faces[0], V.VFS_SET_FACE_Y: g.faces[1],
+            V.VFS_SET_NODE: (0, 0)}
+    for sid, st in sets.items():
+        wl = ctx.vfs_get_weights(sid, V.VFS_WEIGHT_LIQUID)
+        assert np.array_equal(wl, asm.W[st][0]), (name, sid)
+        wf = ctx.vfs_get_weights(sid, V.VFS_WEIGHT_FLUID)
+        if st in g.faces:
+            a = g.faces.index(st)
+            lo, hi = g.face_offsets()[a]
+            assert np.array_equal(g.flat(wf), asm.wf_f[lo:hi]), (name, sid)
+        else:
+            assert np.array_equal(wf, asm.W[st][1]), (name, sid)
+    act = ctx.vfs_get_active()
+    assert np.array_equal(act, asm.active), (name, int((act != asm.active).sum()))
+    assert ctx.vfs_get_stats()["n_active"] == int(asm.active.sum())
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rhs_and_apply(name):
+    _banner(f"rhs/apply {name}")
+    case = CASES[name]()
+    asm = system.assemble(case)
+    ctx = gpu_run(case, step=False)
+    b = ctx.vfs_get_rhs()
+    scale = max(np.abs(asm.b_full).max(), 1e-300)
+    assert np.abs(b - asm.b_full).max() <= 1e-12 * scale
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        x = rng.normal(size=asm.grid.n_samples())
+        y = ctx.vfs_apply(x)
+        ref = system.apply(asm, x)
+        assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step_fp64_matches_oracle(name):
+    _banner(f"step fp64 {name}")
+    case = CASES[name]()
+    asm, x, u = oracle(case)
+    ctx = gpu_run(case, tol=1e-11)
+    st = ctx.vfs_get_stats()
+    assert st["rel_residual"] <= 1e-11
+    ug = flat_faces(asm.grid, ctx.vfs_get_velocity())
+    err = velocity_rel_linf(asm, ug, u)
+    _banner(f"  iters {st['iterations']} rel_res {st['rel_residual']:.2e} vel err {err:.2e}")
+    assert err <= 1e-6
+    # residual of the GPU solution measured by the oracle
+    xg = ctx.vfs_get_solution()
+    assert system.true_relative_residual(asm, xg) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["config1", "ragged130x67", "E2_64"])
+def test_step_mixed_matches_oracle(name):
+    _banner(f"step mixed {name}")
+    case = CASES[name]()
+    asm, x, u = oracle(case)
+    ctx = gpu_run(case, precision=1, tol=1e-9)
+    st = ctx.vfs_get_stats()
+    ug = flat_faces(asm.grid, ctx.vfs_get_velocity())
+    err = velocity_rel_linf(asm, ug, u)
+    _banner(f"  iters {st['iterations']} outer {st['outer_iterations']} rel_res {st['rel_residual']:.2e} vel err {err:.2e}")
+    assert st["rel_residual"] <= 1e-9
+    assert err <= 1e-4
+
+
+def test_config2_full_size_mixed():
+    """512^2 pool with moving solid, variable mu and rho, mixed precision at
+    the timing tolerance 1e-6, plus a tighter solve for the 1e-4 velocity bar."""
+    _banner("config2 512^2 mixed")
+    case = cases.config2()
+    asm, x, u = oracle(case)
+    for tol, bar in ((1e-6, None), (1e-9, 1e-4)):
+        ctx = gpu_run(case, precision=1, tol=tol)
+        st = ctx.vfs_get_stats()
+        ug = flat_faces(asm.grid, ctx.vfs_get_velocity())
+        err = velocity_rel_linf(asm, ug, u)
+        xg = ctx.vfs_get_solution()
+        res = system.true_relative_residual(asm, xg)
+        _banner(f"  tol {tol}: iters {st['iterations']} outer {st['outer_iterations']} "
+                f"gpu rel_res {st['rel_residual']:.2e} oracle-measured {res:.2e} vel err {err:.2e} "
+                f"solve {st['t_solve_ms']:.1f} ms")
+        assert st["rel_residual"] <= tol and res <= 1.01 * tol
+        if bar is not None:
+            assert err <= bar
+        ctx.close()
+
+
+def test_determinism_bitwise():
+    _banner("determinism")
+    case = cases.config1()
+    outs = []
+    for _ in range(2):
+        ctx = gpu_run(case, tol=1e-10)
+        outs.append((ctx.vfs_get_solution(), ctx.vfs_get_stats()["iterations"]))
+        ctx.close()
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_no_liquid_and_tiny_grids():
+    _banner("degenerate cases")
+    from paper_1010_2832_amd import vfstokes as V
+    c = cases.config1()
+    c["phi_l"] = np.ones_like(c["phi_l"])        # all air
+    ctx = gpu_run(c)
+    st = ctx.vfs_get_stats()
+    assert st["n_active"] == 0
+    asm, x, u = oracle(c)
+    ug = flat_faces(asm.grid, ctx.vfs_get_velocity())
+    assert np.array_equal(ug, u)
+    for n in (1, 2, 3):
+        c = cases.drop2d(n, seed=n, radius=0.45)
+        asm, x, u = oracle(c)
+        ctx = gpu_run(c, tol=1e-12)
+        ug = flat_faces(asm.grid, ctx.vfs_get_velocity())
+        assert np.abs(ug - u).max() <= 1e-9 * max(1.0, np.abs(u).max())
+
+
+def test_error_paths():
+    _banner("error paths")
+    from paper_1010_2832_amd import vfstokes as V
+    c = cases.config1()
+    ctx = V.Context(2, c["n"], c["h"])
+    bad = c["phi_l"].copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(V.VfsError) as e:
+        ctx.vfs_set_level_sets(bad)
+    assert e.value.code == V.VFS_EINVAL
+    rho = c["rho"].copy()
+    rho[0, 0] = 0.0
+    with pytest.raises(V.VfsError) as e:
+        ctx.vfs_set_density(rho)
+    assert e.value.code == V.VFS_EINVAL
+    with pytest.raises(V.VfsError) as e:
+        ctx.vfs_step(0.01)          # inputs missing
+    assert e.value.code == V.VFS_ESTATE
+    ctx2 = gpu_run(c, step=False)
+    with pytest.raises(V.VfsError) as e:
+        ctx2.vfs_step(-1.0)
+    assert e.value.code == V.VFS_EINVAL
+    ctx2.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_FP64, 1e-14, 1, 1e-3)
+    rc = ctx2.vfs_step(0.01, allow_unconverged=True)
+    assert rc == V.VFS_ENOTCONV
+    assert ctx2.vfs_get_stats()["iterations"] == 1
+
+
+def test_device_pointer_inputs_match_host_inputs():
+    """Inputs passed as device tensors (already in HBM) give the same step."""
+    import torch
+    _banner("device pointers")
+    case = cases.config1()
+    ctx = gpu_run(case, tol=1e-10)
+    ref = flat_faces(system.Grid(case["n"], case["h"]), ctx.vfs_get_velocity())
+    from paper_1010_2832_amd import vfstokes as V
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float64).ravel(order="F"))).cuda()
+    c2 = V.Context(2, case["n"], case["h"])
+    c2.vfs_set_level_sets(d(case["phi_l"]), d(case["phi_s"]))
+    c2.vfs_set_density(d(case["rho"]))
+    c2.vfs_set_viscosity(d(case["mu"]))
+    c2.vfs_set_velocity([d(q) for q in case["u"]])
+    c2.vfs_set_solid_velocity(None)
+    c2.vfs_set_gravity(case["g"])
+    c2.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_FP64, 1e-10, 100000, 1e-3)
+    c2.vfs_step(case["dt"])
+    got = flat_faces(system.Grid(case["n"], case["h"]), c2.vfs_get_velocity())
+    assert np.array_equal(got, ref)
