@@ -44,6 +44,29 @@ def algorithmic_bytes(dim, precision, n_active):
     return (5.0 + c) * word * n_active, 7.0 * word * n_active
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "k_apply2d_pool512_mixed_counters.md")
+KERNEL_SOURCES = ("paper_1010_2832_amd/csrc/k_pcg.hip", "paper_1010_2832_amd/csrc/vfs_reduce.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the 2D apply kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources
+    changed since the counters were taken (or the summary is absent)."""
+    import hashlib
+    import re
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    m = re.search(r"sha256 \(k_pcg.hip \+ vfs_reduce.h\): ([0-9a-f]+)", text)
+    t = re.search(r"HBM traffic per launch \(bytes, scaled\) \| ([0-9.eE+-]+)", text)
+    if not m or not t or m.group(1) != h.hexdigest():
+        return None
+    return float(t.group(1))
+
+
 def cpu_baseline(case, iters, seconds_cap=30.0):
     """The oracle as it stands: assemble the explicit FP64 matrix and run a
     fixed number of Jacobi-PCG iterations; DOF*iter/s on the host."""
@@ -157,7 +180,9 @@ def main():
                    "rel_residual_fp64": res,
                    "assemble_ms": st["t_assemble_ms"], "recover_ms": st["t_recover_ms"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (args.n == 512 and dom.startswith("k_apply2d")
+                                                       and prec == V.VFS_MIXED) else None,
                      "avg_launch_ms": t_ms, "launches_timed": int(st["n_apply_timed"]),
                      "algorithmic_bytes_per_launch": bytes_,
                      "apply_avg_ms": ta, "update_avg_ms": tu},

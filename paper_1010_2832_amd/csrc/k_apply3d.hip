@@ -17,6 +17,8 @@
 #include "vfs_internal.h"
 #include "vfs_reduce.h"
 
+#include <algorithm>
+
 namespace vfs {
 namespace {
 
@@ -24,8 +26,8 @@ constexpr int TX = 64, TY = 4, KZ = 8, NT = 256;
 constexpr int HX = TX + 2, HY = TY + 2;
 constexpr int FX = TX + 1, FY = TY + 1;
 
-__device__ __forceinline__ void tile_origin(const Tiles& t, int& i0, int& j0, int& k0) {
-    const int id = t.list[blockIdx.x];
+__device__ __forceinline__ void tile_origin(const Tiles& t, int w, int& i0, int& j0, int& k0) {
+    const int id = t.list[w];
     const int tx = id % t.ntx;
     const int ty = (id / t.ntx) % t.nty;
     const int tz = id / (t.ntx * t.nty);
@@ -80,15 +82,16 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
     __shared__ T gV[2][FY][FX];
     __shared__ T gW[2][FY][FX];
     const long long NP = g.NP;
-    int i0, j0, k0;
-    tile_origin(tl, i0, j0, k0);
-    const int kend = min(k0 + KZ, g.nz + 1);
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
     Loader<T, MODE, ZIN> ld{g, r, zs, dinv, pin, pout, a, beta, first};
-
+    double acc = 0.0;
+  for (int wtile = blockIdx.x; wtile < tl.count; wtile += gridDim.x) {
+    int i0, j0, k0;
+    tile_origin(tl, wtile, i0, j0, k0);
+    const int kend = min(k0 + KZ, g.nz + 1);
     T vcur[6], acur[6], vnext[6], anext[6];
-
+    __syncthreads();   // LDS of the previous tile is no longer read
     // load weighted plane kk into ring slot kk&1; own anchor values -> vo, ao
     auto load_plane = [&](int kk, T (&vo)[6], T (&ao)[6]) {
         const int sl = kk & 1;
@@ -198,7 +201,6 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
     faces(k0 - 1, true, true);
     __syncthreads();
 
-    double acc = 0.0;
     for (int k = k0; k < kend; ++k) {
         load_plane(k + 1, vnext, anext);
         __syncthreads();
@@ -244,6 +246,7 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
             acur[s] = anext[s];
         }
     }
+  }
     if (MODE == MODE_APPLY) return;
     double vv[1] = {acc};
     block_partial<1, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
@@ -275,12 +278,13 @@ __global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict_
     }
     const T alpha = (T)alpha_d;
     const long long NP = g.NP;
-    int i0, j0, k0;
-    tile_origin(tl, i0, j0, k0);
-    const int kend = min(k0 + KZ, g.nz + 1);
-    const int i = i0 + (threadIdx.x & 63), j = j0 + (threadIdx.x >> 6);
     double rz = 0.0, rr = 0.0;
-    if (i <= g.nx && j <= g.ny) {
+    for (int wtile = blockIdx.x; wtile < tl.count; wtile += gridDim.x) {
+        int i0, j0, k0;
+        tile_origin(tl, wtile, i0, j0, k0);
+        const int kend = min(k0 + KZ, g.nz + 1);
+        const int i = i0 + (threadIdx.x & 63), j = j0 + (threadIdx.x >> 6);
+        if (!(i <= g.nx && j <= g.ny)) continue;
         for (int k = k0; k < kend; ++k) {
             const long long o = g.idx(i, j, k);
 #pragma unroll
@@ -365,7 +369,7 @@ void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* 
                     const T* dinv, const T* pin, T* pout, T* q, const T* a, const T* c,
                     const T* K, const T* bvec, const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    const dim3 gs(tl.count);
+    const dim3 gs(std::min(tl.count, kMaxTileBlocks));
     if (mode == MODE_DIR) {
         if (zin)
             hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
@@ -386,8 +390,8 @@ template <typename T>
 void launch_update3d(const Geo& g, const Tiles& tl, T* x, const T* p, T* r, const T* q,
                      const T* dinv, T* z, const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    hipLaunchKernelGGL((k_update3d<T>), dim3(tl.count), dim3(NT), 0, s, g, tl, x, p, r, q, dinv, z,
-                       ra);
+    hipLaunchKernelGGL((k_update3d<T>), dim3(std::min(tl.count, kMaxTileBlocks)), dim3(NT), 0, s, g,
+                       tl, x, p, r, q, dinv, z, ra);
 }
 
 #define VFS_INST3(T)                                                                           \

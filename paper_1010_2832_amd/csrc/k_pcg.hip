@@ -11,24 +11,30 @@
 //          q = A p, partials of p.q.
 //   update: sum the p.q partials, alpha = r.z / p.q; x += alpha p,
 //          r -= alpha q, z = D^-1 r, partials of r.z and r.r.
-// The 2D apply is one fused LDS-tiled stencil: a 64x4 tile stages the
-// weighted samples of its (66x6) halo in LDS, forms the face values g on the
-// (65x5) faces it needs, then the sample outputs.  All reductions are FP64
+// The 2D apply is one fused LDS-tiled stencil: a 64x8 tile stages the
+// weighted samples of its (66x10) halo in LDS, forms the face values g on the
+// (65x9) faces it needs, then the sample outputs (two rows per thread).  All reductions are FP64
 // and deterministic (see vfs_reduce.h).
 #include "vfs_internal.h"
 #include "vfs_reduce.h"
+
+#include <algorithm>
 
 namespace vfs {
 namespace {
 
 constexpr int BX = 64;
-constexpr int BY = 4;
+constexpr int BY = 8;
 constexpr int NT = 256;
+constexpr int RPT = BY * BX / NT;   // anchor rows per thread in the output stage
 
 // ---------------------------------------------------------------------------
 // 2D fused apply.  Sample slices: 0 p (cell), 1 tau_xx (cell), 2 tau_xy (node);
 // face slices: 0 u, 1 v.  K already carries dt/h^2.
 // ---------------------------------------------------------------------------
+// Latency structure: every global load that does not depend on the r.z /
+// r.r totals (partials, halo values, K, a, c) is issued before the totals
+// are formed, so one memory round trip covers the whole kernel.
 template <typename T, int MODE, bool ZIN>
 __global__ __launch_bounds__(NT) void k_apply2d(Geo g, const T* __restrict__ r,
                                                 const T* __restrict__ zs,
@@ -37,16 +43,10 @@ __global__ __launch_bounds__(NT) void k_apply2d(Geo g, const T* __restrict__ r,
                                                 T* __restrict__ q, const T* __restrict__ a,
                                                 const T* __restrict__ c, const T* __restrict__ K,
                                                 const T* __restrict__ bv, RedArgs ra) {
+    constexpr int NE1 = ((BX + 2) * (BY + 2) + NT - 1) / NT;   // halo elements per thread
+    constexpr int NE2 = ((BX + 1) * (BY + 1) + NT - 1) / NT;   // faces per thread
     const int bid = blockIdx.x + gridDim.x * blockIdx.y;
-    T beta = T(0);
-    bool first = true;
-    if (MODE == MODE_DIR) {
-        if (ra.sc->done) return;
-        double bd;
-        if (!cg_direction_preamble<NT>(ra, bid, bd)) return;
-        first = ra.kidx == 0;
-        beta = (T)bd;
-    }
+    if (MODE == MODE_DIR && ra.sc->done) return;
     __shared__ T sW[3][BY + 2][BX + 2];
     __shared__ T sV[3][BY + 2][BX + 2];
     __shared__ T sG[2][BY + 1][BX + 1];
@@ -54,88 +54,143 @@ __global__ __launch_bounds__(NT) void k_apply2d(Geo g, const T* __restrict__ r,
     const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
     const int tid = threadIdx.x;
 
-    // stage 1: direction (or input) values and weighted values on the halo
-    for (int e = tid; e < (BX + 2) * (BY + 2); e += NT) {
+    // (1) partial sums of the previous kernel
+    PartialLoads<2, NT, 4> pl;
+    if (MODE == MODE_DIR) pl.load(ra.part_in, ra.nb_in);
+
+    // (2) independent loads: halo raw values, face K, output a and c
+    T Rr[NE1][3], Dd[NE1][3], Pp[NE1][3], Aa[NE1][3];
+    bool in1[NE1], own1[NE1];
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+        const int e = tid + m * NT;
         const int li = e % (BX + 2), lj = e / (BX + 2);
         const int i = i0 - 1 + li, j = j0 - 1 + lj;
-        T v[3] = {T(0), T(0), T(0)};
-        T w[3] = {T(0), T(0), T(0)};
-        if (i <= g.nx + 1 && j <= g.ny + 1) {
-            const long long o = g.idx(i, j);
-            const bool own = li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
-#pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const long long os = o + s * NP;
-                T val;
-                if (MODE == MODE_DIR) {
-                    const T z = ZIN ? zs[os] : dinv[os] * r[os];
-                    val = first ? z : z + beta * pin[os];
-                    if (own) pout[os] = val;
-                } else {
-                    val = pin[os];
-                }
-                v[s] = val;
-                w[s] = a[os] * val;
-            }
-        }
+        in1[m] = e < (BX + 2) * (BY + 2) && i <= g.nx + 1 && j <= g.ny + 1;
+        own1[m] = in1[m] && li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
+        const long long o = in1[m] ? g.idx(i, j) : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            sV[s][lj][li] = v[s];
-            sW[s][lj][li] = w[s];
+            const long long os = o + s * NP;
+            Rr[m][s] = Dd[m][s] = Pp[m][s] = Aa[m][s] = T(0);
+            if (in1[m]) {
+                if (MODE == MODE_DIR) {
+                    Rr[m][s] = ZIN ? zs[os] : r[os];
+                    if (!ZIN) Dd[m][s] = dinv[os];
+                }
+                Pp[m][s] = pin[os];
+                Aa[m][s] = a[os];
+            }
         }
     }
-    __syncthreads();
-
-    // stage 2: g = K (B x) on u faces (i0..i0+BX, j0-1..j0+BY-1) and
-    //          v faces (i0-1..i0+BX-1, j0..j0+BY)
-    for (int e = tid; e < (BX + 1) * (BY + 1); e += NT) {
+    T Ku[NE2], Kv[NE2];
+#pragma unroll
+    for (int m = 0; m < NE2; ++m) {
+        const int e = tid + m * NT;
         const int li = e % (BX + 1), lj = e / (BX + 1);
-        {
-            const int i = i0 + li, j = j0 - 1 + lj;
-            T gv = T(0);
-            if (i <= g.nx && j >= 0 && j < g.ny) {
-                const T k = K[g.idx(i, j)];
-                gv = k * ((sW[0][lj][li + 1] - sW[0][lj][li]) + (sW[1][lj][li] - sW[1][lj][li + 1]) +
-                          (sW[2][lj][li + 1] - sW[2][lj + 1][li + 1]));
-            }
-            sG[0][lj][li] = gv;
+        Ku[m] = Kv[m] = T(0);
+        if (e < (BX + 1) * (BY + 1)) {
+            const int iu = i0 + li, ju = j0 - 1 + lj;
+            if (iu <= g.nx && ju >= 0 && ju < g.ny) Ku[m] = K[g.idx(iu, ju)];
+            const int iv = i0 - 1 + li, jv = j0 + lj;
+            if (iv >= 0 && iv < g.nx && jv <= g.ny) Kv[m] = K[NP + g.idx(iv, jv)];
         }
-        {
-            const int i = i0 - 1 + li, j = j0 + lj;
-            T gv = T(0);
-            if (i >= 0 && i < g.nx && j <= g.ny) {
-                const T k = K[NP + g.idx(i, j)];
-                gv = k * ((sW[0][lj + 1][li] - sW[0][lj][li]) + (sW[1][lj + 1][li] - sW[1][lj][li]) +
-                          (sW[2][lj + 1][li] - sW[2][lj + 1][li + 1]));
+    }
+    const int tx = tid % BX;
+    T Ao[RPT][3], Co[RPT][2], Bo[RPT][3];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = tid / BX + rr * (NT / BX);
+        const int i = i0 + tx, j = j0 + ty;
+        const bool ok = i <= g.nx && j <= g.ny;
+        const long long o = ok ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            Ao[rr][s] = ok ? a[o + s * NP] : T(0);
+            Bo[rr][s] = (MODE == MODE_RESID && ok) ? bv[o + s * NP] : T(0);
+        }
+        Co[rr][0] = ok ? c[NP + o] : T(0);
+        Co[rr][1] = ok ? c[2 * NP + o] : T(0);
+    }
+
+    // (3) totals -> beta
+    T beta = T(0);
+    bool first = true;
+    if (MODE == MODE_DIR) {
+        double tot[2];
+        pl.finish(tot);
+        double bd;
+        if (!cg_direction_decide(ra, bid, tot[0], tot[1], bd)) return;
+        first = ra.kidx == 0;
+        beta = (T)bd;
+    }
+
+    // (4) stage 1: direction values and weighted values on the halo
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+        const int e = tid + m * NT;
+        if (e >= (BX + 2) * (BY + 2)) continue;
+        const int li = e % (BX + 2), lj = e / (BX + 2);
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        const long long o = in1[m] ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            T val;
+            if (MODE == MODE_DIR) {
+                const T z = ZIN ? Rr[m][s] : Dd[m][s] * Rr[m][s];
+                val = first ? z : z + beta * Pp[m][s];
+                if (own1[m]) pout[o + s * NP] = val;
+            } else {
+                val = Pp[m][s];
             }
-            sG[1][lj][li] = gv;
+            sV[s][lj][li] = val;
+            sW[s][lj][li] = Aa[m][s] * val;
         }
     }
     __syncthreads();
 
-    // stage 3: y = B^T g + Dg x at the tile's anchors
-    const int tx = tid % BX, ty = tid / BX;
-    const int i = i0 + tx, j = j0 + ty;
+    // (5) stage 2: g = K (B x) on u faces (i0..i0+BX, j0-1..j0+BY-1) and
+    //     v faces (i0-1..i0+BX-1, j0..j0+BY)
+#pragma unroll
+    for (int m = 0; m < NE2; ++m) {
+        const int e = tid + m * NT;
+        if (e >= (BX + 1) * (BY + 1)) continue;
+        const int li = e % (BX + 1), lj = e / (BX + 1);
+        sG[0][lj][li] = Ku[m] * ((sW[0][lj][li + 1] - sW[0][lj][li]) +
+                                 (sW[1][lj][li] - sW[1][lj][li + 1]) +
+                                 (sW[2][lj][li + 1] - sW[2][lj + 1][li + 1]));
+        sG[1][lj][li] = Kv[m] * ((sW[0][lj + 1][li] - sW[0][lj][li]) +
+                                 (sW[1][lj + 1][li] - sW[1][lj][li]) +
+                                 (sW[2][lj + 1][li] - sW[2][lj + 1][li + 1]));
+    }
+    __syncthreads();
+
+    // (6) stage 3: y = B^T g + Dg x at the tile's anchors (RPT rows per thread)
     double acc = 0.0;
-    if (i <= g.nx && j <= g.ny) {
-        const long long o = g.idx(i, j);
-        const T gu0 = sG[0][ty + 1][tx], gu1 = sG[0][ty + 1][tx + 1], gum = sG[0][ty][tx];
-        const T gv0 = sG[1][ty][tx + 1], gv1 = sG[1][ty + 1][tx + 1], gvm = sG[1][ty][tx];
-        const T v0 = sV[0][ty + 1][tx + 1], v1 = sV[1][ty + 1][tx + 1], v2 = sV[2][ty + 1][tx + 1];
-        const T y0 = a[o] * ((gu0 - gu1) + (gv0 - gv1));
-        const T y1 = a[NP + o] * ((gu1 - gu0) + (gv0 - gv1)) + c[NP + o] * v1;
-        const T y2 = a[2 * NP + o] * ((gu0 - gum) + (gv0 - gvm)) + c[2 * NP + o] * v2;
-        if (MODE == MODE_RESID) {
-            const T r0 = bv[o] - y0, r1 = bv[NP + o] - y1, r2 = bv[2 * NP + o] - y2;
-            q[o] = r0;
-            q[NP + o] = r1;
-            q[2 * NP + o] = r2;
-            acc = (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
-        } else {
-            q[o] = y0;
-            q[NP + o] = y1;
-            q[2 * NP + o] = y2;
-            if (MODE == MODE_DIR) acc = (double)v0 * y0 + (double)v1 * y1 + (double)v2 * y2;
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = tid / BX + rr * (NT / BX);
+        const int i = i0 + tx, j = j0 + ty;
+        if (i <= g.nx && j <= g.ny) {
+            const long long o = g.idx(i, j);
+            const T gu0 = sG[0][ty + 1][tx], gu1 = sG[0][ty + 1][tx + 1], gum = sG[0][ty][tx];
+            const T gv0 = sG[1][ty][tx + 1], gv1 = sG[1][ty + 1][tx + 1], gvm = sG[1][ty][tx];
+            const T v0 = sV[0][ty + 1][tx + 1], v1 = sV[1][ty + 1][tx + 1], v2 = sV[2][ty + 1][tx + 1];
+            const T y0 = Ao[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
+            const T y1 = Ao[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * v1;
+            const T y2 = Ao[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * v2;
+            if (MODE == MODE_RESID) {
+                const T r0 = Bo[rr][0] - y0, r1 = Bo[rr][1] - y1, r2 = Bo[rr][2] - y2;
+                q[o] = r0;
+                q[NP + o] = r1;
+                q[2 * NP + o] = r2;
+                acc += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
+            } else {
+                q[o] = y0;
+                q[NP + o] = y1;
+                q[2 * NP + o] = y2;
+                if (MODE == MODE_DIR) acc += (double)v0 * y0 + (double)v1 * y1 + (double)v2 * y2;
+            }
         }
     }
     if (MODE == MODE_APPLY) return;
@@ -146,16 +201,33 @@ __global__ __launch_bounds__(NT) void k_apply2d(Geo g, const T* __restrict__ r,
 // ---------------------------------------------------------------------------
 // pointwise kernels over whole padded vectors (n = nsamp * NP elements)
 // ---------------------------------------------------------------------------
+// The first EPT elements of every thread are loaded before the p.q total is
+// formed (latency hiding); the rest, if any, follow in a grid-stride loop.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update(long long n, T* __restrict__ x,
                                                const T* __restrict__ p, T* __restrict__ r,
                                                const T* __restrict__ q,
                                                const T* __restrict__ dinv, T* __restrict__ z,
                                                RedArgs ra) {
+    constexpr int EPT = 8;
     Scalars* sc = ra.sc;
     if (sc->done) return;
+    PartialLoads<1, NT, 6> pl;
+    pl.load(ra.part_in, ra.nb_in);
+    const long long base = (long long)blockIdx.x * NT * EPT + threadIdx.x;
+    T X[EPT], P[EPT], R[EPT], Q[EPT], D[EPT];
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+        const long long t = base + (long long)m * NT;
+        const bool ok = t < n;
+        X[m] = ok ? x[t] : T(0);
+        P[m] = ok ? p[t] : T(0);
+        R[m] = ok ? r[t] : T(0);
+        Q[m] = ok ? q[t] : T(0);
+        D[m] = ok ? dinv[t] : T(0);
+    }
     double tot[1];
-    reduce_partials<1, NT>(ra.part_in, ra.nb_in, tot);
+    pl.finish(tot);
     const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -171,15 +243,32 @@ __global__ __launch_bounds__(NT) void k_update(long long n, T* __restrict__ x,
     }
     const T alpha = (T)alpha_d;
     double rz = 0.0, rr = 0.0;
-    const long long stride = (long long)gridDim.x * NT;
-    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < n; t += stride) {
-        const T ri = r[t] - alpha * q[t];
-        const T zi = dinv[t] * ri;
-        x[t] = x[t] + alpha * p[t];
-        r[t] = ri;
-        if (z) z[t] = zi;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
+#pragma unroll
+    for (int m = 0; m < EPT; ++m) {
+        const long long t = base + (long long)m * NT;
+        if (t < n) {
+            const T ri = R[m] - alpha * Q[m];
+            const T zi = D[m] * ri;
+            x[t] = X[m] + alpha * P[m];
+            r[t] = ri;
+            if (z) z[t] = zi;
+            rz += (double)ri * (double)zi;
+            rr += (double)ri * (double)ri;
+        }
+    }
+    const long long stride = (long long)gridDim.x * NT * EPT;
+    for (long long t0 = base + stride; t0 < n; t0 += stride) {
+        for (int m = 0; m < EPT; ++m) {
+            const long long t = t0 + (long long)m * NT;
+            if (t >= n) break;
+            const T ri = r[t] - alpha * q[t];
+            const T zi = dinv[t] * ri;
+            x[t] = x[t] + alpha * p[t];
+            r[t] = ri;
+            if (z) z[t] = zi;
+            rz += (double)ri * (double)zi;
+            rr += (double)ri * (double)ri;
+        }
     }
     double vv[2] = {rz, rr};
     block_partial<2, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
@@ -290,18 +379,18 @@ int apply_grid_blocks(const Geo& g) {
 
 int vec_grid_blocks(const Geo& g) {
     const long long n = (long long)g.nsamp() * g.NP;
-    long long nb = (n + NT * 4 - 1) / (NT * 4);
+    long long nb = (n + NT * 8 - 1) / (NT * 8);
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     return (int)nb;
 }
 
 int apply_blocks(const Geo& g, const Tiles& tl) {
-    return g.dim == 2 ? apply_grid_blocks(g) : tl.count;
+    return g.dim == 2 ? apply_grid_blocks(g) : std::min(tl.count, kMaxTileBlocks);
 }
 
 int update_blocks(const Geo& g, const Tiles& tl) {
-    return g.dim == 2 ? vec_grid_blocks(g) : tl.count;
+    return g.dim == 2 ? vec_grid_blocks(g) : std::min(tl.count, kMaxTileBlocks);
 }
 
 template <typename T>

@@ -26,6 +26,9 @@
 namespace vfs {
 
 constexpr int kFront = 16;
+// 3D kernels run at most this many workgroups, each looping over tiles, so
+// that the partial sums a consumer must read stay few.
+constexpr int kMaxTileBlocks = 1536;
 
 struct Geo {
     int dim;

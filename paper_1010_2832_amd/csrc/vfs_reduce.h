@@ -71,6 +71,77 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
     __syncthreads();
 }
 
+// Split form of reduce_partials for latency hiding: load the (at most
+// MAXP * NT per value) partials into registers first, issue independent
+// global loads, then finish.  Same order of additions as reduce_partials.
+template <int NV, int NT, int MAXP>
+struct PartialLoads {
+    double v[NV][MAXP];
+    const double* src = nullptr;
+    int n = 0;
+    __device__ __forceinline__ void load(const double* __restrict__ part, int nb) {
+        src = part;
+        n = nb;
+#pragma unroll
+        for (int m = 0; m < MAXP; ++m) {
+            const int b = threadIdx.x + m * NT;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q][m] = b < nb ? part[(long long)q * nb + b] : 0.0;
+        }
+    }
+    __device__ __forceinline__ void finish(double (&tot)[NV]) {
+        constexpr int NW = NT / 64;
+        __shared__ double sr[NV][NW];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < MAXP; ++m) s += v[q][m];
+            // partials beyond the register window (large grids)
+            for (int b = threadIdx.x + MAXP * NT; b < n; b += NT) s += src[(long long)q * n + b];
+            s = wave_sum64(s);
+            if (lane == 0) sr[q][wid] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = sr[q][0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) s += sr[q][w];
+            tot[q] = s;
+        }
+        __syncthreads();
+    }
+};
+
+// Decision of a MODE_DIR apply from the r.z / r.r totals: returns false if
+// the solve stops here (converged, iteration cap, non-finite); sets beta.
+__device__ __forceinline__ bool cg_direction_decide(const RedArgs& ra, int bid, double rzk,
+                                                    double rrk, double& beta) {
+    Scalars* sc = ra.sc;
+    const double bb = ra.set_bb ? rrk : sc->bb;
+    int stop = 0;
+    if (!isfinite(rzk) || !isfinite(rrk))
+        stop = 3;
+    else if (rrk <= sc->tol2 * bb)
+        stop = 1;
+    else if (ra.kidx >= sc->max_iter)
+        stop = 2;
+    beta = ra.kidx == 0 ? 0.0 : rzk / sc->rz[(ra.kidx + 1) & 1];
+    if (bid == 0 && threadIdx.x == 0) {
+        sc->rz[ra.kidx & 1] = rzk;
+        sc->rr = rrk;
+        sc->beta = beta;
+        if (ra.set_bb) sc->bb = bb;
+        if (stop) {
+            sc->done = stop;
+            sc->iter = ra.kidx;
+        }
+    }
+    return stop == 0;
+}
+
 // Shared preamble of a MODE_DIR apply: returns false if the solve stops here
 // (converged, iteration cap, non-finite); sets beta.
 template <int NT>
