@@ -184,6 +184,65 @@ int vfs_set_profiling(vfs_ctx* ctx, int on);
 /* Number of entries of a sample-order vector and of the face vector. */
 int vfs_get_sizes(const vfs_ctx* ctx, int64_t* n_samples, int64_t* n_faces);
 
+/* ------------------------------------------------------------------------
+ * Batched 2D steps: many independent problems of different sizes.  Their
+ * CG solves run in one persistent launch per refinement pass (FP32 Jacobi
+ * PCG with FP64 reductions inside, FP64 residual and refinement between
+ * passes); each pass is captured once in a hipGraph and replayed.  Every
+ * problem is a full step of the method above (same equations, inputs and
+ * outputs as a single context), always in VFS_MIXED arithmetic.
+ * ------------------------------------------------------------------------ */
+typedef struct vfs_batch vfs_batch;
+
+typedef struct vfs_batch_stats {
+    int32_t n_problems;
+    int32_t variant;          /* tile shape index (vfs_batch_variant_shape) */
+    int32_t blocks_per_cu;    /* persistent workgroups per compute unit */
+    int32_t grid;             /* persistent workgroups launched */
+    int32_t graph_used;       /* 1 if the pass ran from a hipGraph */
+    int32_t status;           /* VFS_OK or VFS_ENOTCONV */
+    int64_t n_active_total;   /* sum of active unknowns */
+    int64_t dof_iters;        /* sum over problems of active unknowns x CG iterations */
+    int32_t max_iterations;   /* largest per-problem CG iteration count */
+    int32_t passes_max;       /* largest per-problem refinement pass count */
+    double  t_assemble_ms, t_solve_ms, t_step_ms;   /* device time of the last step */
+    double  latency_p50_ms, latency_p90_ms, latency_p99_ms, latency_max_ms;
+                              /* per-problem solve latency: device wall clock from
+                                 the start of the solve to the pass that met tol */
+} vfs_batch_stats;
+
+const char* vfs_batch_last_error(const vfs_batch* b);
+/* n problems; problem i has nx[i] x ny[i] cells of size h[i], origin 0. */
+int vfs_batch_create(vfs_batch** out, int n, const int* nx, const int* ny, const double* h);
+int vfs_batch_destroy(vfs_batch* b);
+/* NULL selects the batch's own (non-blocking, default priority) stream. */
+int vfs_batch_set_stream(vfs_batch* b, void* hip_stream);
+/* Inputs of problem i, same meaning and layout as vfs_set_level_sets,
+ * vfs_set_density, vfs_set_viscosity, vfs_set_velocity,
+ * vfs_set_solid_velocity (ub/vb may be NULL) and vfs_set_gravity. */
+int vfs_batch_set_problem(vfs_batch* b, int i, const double* phi_liquid, const double* phi_solid,
+                          const double* rho, const double* mu, const double* u, const double* v,
+                          const double* ub, const double* vb, const double* g);
+int vfs_batch_set_solver(vfs_batch* b, double rel_tol, int max_iter, double w_min);
+/* Launch configuration: tile shape variant and persistent workgroups per
+ * compute unit (clamped to the occupancy limit); chosen by the autotuner. */
+int vfs_batch_num_variants(void);
+int vfs_batch_variant_shape(int variant, int* bx, int* by);
+int vfs_batch_set_tiles(vfs_batch* b, int variant, int blocks_per_cu);
+/* Autotuner probe: device time per CG iteration of the persistent kernel
+ * for a configuration, measured over `iterations` iterations on the
+ * currently assembled problems (requires one vfs_batch_step before). */
+int vfs_batch_time_variant(vfs_batch* b, int variant, int blocks_per_cu, int iterations,
+                           double* ms_per_iteration);
+/* One step of every problem: assemble all, solve all, recover all velocities.
+ * VFS_ENOTCONV if some problem missed the tolerance (its best iterate is used). */
+int vfs_batch_step(vfs_batch* b, double dt);
+int vfs_batch_get_velocity(vfs_batch* b, int i, double* u, double* v);
+int vfs_batch_get_solution(vfs_batch* b, int i, double* x);   /* sample order */
+int vfs_batch_get_problem(vfs_batch* b, int i, int* iterations, int* passes,
+                          double* rel_residual, double* latency_ms, int64_t* n_active);
+int vfs_batch_get_stats(vfs_batch* b, vfs_batch_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

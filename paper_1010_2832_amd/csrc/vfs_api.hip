@@ -419,6 +419,9 @@ int unpack_samples(vfs_ctx* ctx, const double* src, double* user) {
 // ---------------------------------------------------------------------------
 namespace vfs {
 
+int ctx_assemble(vfs_ctx* ctx, double dt) { return assemble_internal(ctx, dt); }
+int ctx_recover(vfs_ctx* ctx) { return recover_internal(ctx); }
+
 Geo make_geo(int dim, int nx, int ny, int nz, double h) {
     Geo g{};
     g.dim = dim;

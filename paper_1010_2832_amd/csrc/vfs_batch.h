@@ -1,0 +1,84 @@
+// Batched 2D solves (one persistent launch for many problems): device
+// structures shared by k_batch.hip and vfs_batch.hip.
+#pragma once
+
+#include "vfs_internal.h"
+
+namespace vfs {
+
+constexpr int kBatchVariants = 4;   // tile shapes (BX x BY): 64x4, 64x8, 32x8, 128x2
+
+// One problem as seen by the batched kernels (pointers into its context).
+struct BProb {
+    Geo g;
+    int item0, nt, ntx, nty;      // first work item, tiles (items) of this problem
+    float *x32, *r32, *p0, *p1, *q32;
+    const float *a, *c, *K, *dinv;
+    double *x64, *r64;
+    const double *a64, *c64, *K64, *b64;
+};
+
+// Per-problem mode inside the persistent solve.  The owner item writes the
+// mode of the next phase into slot (phase+1)&1 while every item reads slot
+// phase&1, so a mode change never races with the problem's other items.
+enum BMode : int { BM_CG = 0, BM_AXPY = 1, BM_RESID = 2, BM_DECIDE = 3, BM_DONE = 4 };
+struct BPhase {
+    int mode;
+    int kloc;   // CG iteration within the current inner solve
+};
+
+// Per-problem solver state (written by the owner item / finalize workgroup;
+// a field is never written in the phase in which the problem's other items
+// read it).
+struct BState {
+    BPhase ph[2];
+    double rz[2];
+    double bb;        // |r32|^2 at the start of the pass (1 up to rounding)
+    double rho2;      // |r64|^2 of the current iterate
+    double bb64;      // |b|^2
+    double rel;       // FP64 true relative residual
+    double tol_in2;   // inner (FP32) relative tolerance squared for the next pass
+    int needs;        // 1: the problem needs a solve (set before the persistent launch)
+    int last_iter;    // iterations of the last inner solve
+    int iters_total;  // iterations over all passes
+    int passes;
+    unsigned long long t_start, t_done;   // device wall clock
+};
+
+struct BatchCtl {
+    unsigned bar_count;
+    unsigned bar_gen;
+    int abort;
+    int n_done;
+    int n_need;
+    int pad;
+    unsigned long long spin_ticks;   // barrier wait deadline (wall-clock ticks)
+};
+
+struct BatchArgs {
+    BProb* prob;
+    BState* state;
+    BatchCtl* ctl;
+    const int* item_prob;
+    int nitems, nprob;
+    double *partA, *partB, *partR;
+    double tol;
+    int max_iter, max_iter_pass, max_passes;
+    int first_pass;
+    int bx, by;
+};
+
+void batch_tile_shape(int variant, int* bx, int* by);
+size_t batch_lds_bytes(int variant, int word);
+int batch_pcg_occupancy(int variant, int* blocks_per_cu);
+void launch_batch_pcg(int variant, const BatchArgs& A, int grid, hipStream_t s);
+void launch_batch_resid(int variant, const BatchArgs& A, int grid, hipStream_t s);
+void launch_batch_finalize(const BatchArgs& A, hipStream_t s);
+void launch_batch_zero_x(const BatchArgs& A, int grid, hipStream_t s);
+void launch_batch_reset_ctl(BatchCtl* ctl, hipStream_t s);
+
+// single-problem pieces reused by the batch (vfs_api.hip)
+int ctx_assemble(vfs_ctx* ctx, double dt);
+int ctx_recover(vfs_ctx* ctx);
+
+}  // namespace vfs

@@ -42,6 +42,21 @@ class vfs_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class vfs_batch_stats(ctypes.Structure):
+    _fields_ = [("n_problems", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("graph_used", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("n_active_total", ctypes.c_int64), ("dof_iters", ctypes.c_int64),
+                ("max_iterations", ctypes.c_int32), ("passes_max", ctypes.c_int32),
+                ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("t_step_ms", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
+                ("latency_p90_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
+                ("latency_max_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class VfsError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_CODES.get(code, code)}: {msg}")
@@ -89,6 +104,22 @@ _SIGS = {
     "vfs_get_stats": ([_P, ctypes.POINTER(vfs_stats)], _I),
     "vfs_get_sizes": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "vfs_set_profiling": ([_P, _I], _I),
+    "vfs_batch_last_error": ([_P], ctypes.c_char_p),
+    "vfs_batch_create": ([ctypes.POINTER(_P), _I, _P, _P, _P], _I),
+    "vfs_batch_destroy": ([_P], _I),
+    "vfs_batch_set_stream": ([_P, _P], _I),
+    "vfs_batch_set_problem": ([_P, _I, _P, _P, _P, _P, _P, _P, _P, _P, _P], _I),
+    "vfs_batch_set_solver": ([_P, _D, _I, _D], _I),
+    "vfs_batch_num_variants": ([], _I),
+    "vfs_batch_variant_shape": ([_I, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
+    "vfs_batch_set_tiles": ([_P, _I, _I], _I),
+    "vfs_batch_time_variant": ([_P, _I, _I, _I, ctypes.POINTER(_D)], _I),
+    "vfs_batch_step": ([_P, _D], _I),
+    "vfs_batch_get_velocity": ([_P, _I, _P, _P], _I),
+    "vfs_batch_get_solution": ([_P, _I, _P], _I),
+    "vfs_batch_get_problem": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D),
+                               ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)], _I),
+    "vfs_batch_get_stats": ([_P, ctypes.POINTER(vfs_batch_stats)], _I),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -347,3 +378,120 @@ def context_from_case(case, precision=VFS_FP64, tol=None, max_iter=200000, w_min
     ctx.vfs_set_solver(VFS_PRECOND_JACOBI, precision, tol if tol is not None else case.get("tol", 1e-6),
                        max_iter, w_min)
     return ctx
+
+
+# ---------------------------------------------------------------------------
+# batched 2D steps
+# ---------------------------------------------------------------------------
+def _bcheck(b, rc, allow=(VFS_OK,)):
+    if rc not in allow:
+        raise VfsError(rc, _lib.vfs_batch_last_error(b).decode())
+    return rc
+
+
+def vfs_batch_num_variants():
+    return _lib.vfs_batch_num_variants()
+
+
+def vfs_batch_variant_shape(variant):
+    bx, by = _I(), _I()
+    _bcheck(None, _lib.vfs_batch_variant_shape(variant, ctypes.byref(bx), ctypes.byref(by)))
+    return bx.value, by.value
+
+
+class Batch:
+    """Owns one vfs_batch: n independent 2D problems (sizes n_i x m_i)."""
+
+    def __init__(self, sizes, hs):
+        self.sizes = [tuple(int(q) for q in s) for s in sizes]
+        n = len(self.sizes)
+        nx = (ctypes.c_int * n)(*[s[0] for s in self.sizes])
+        ny = (ctypes.c_int * n)(*[s[1] for s in self.sizes])
+        h = (ctypes.c_double * n)(*[float(q) for q in hs])
+        out = _P()
+        rc = _lib.vfs_batch_create(ctypes.byref(out), n, ctypes.cast(nx, _P), ctypes.cast(ny, _P),
+                                   ctypes.cast(h, _P))
+        if rc != VFS_OK:
+            raise VfsError(rc, _lib.vfs_batch_last_error(None).decode())
+        self.handle = out
+        self.n = n
+
+    def close(self):
+        if self.handle:
+            _lib.vfs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vfs_batch_set_stream(self, stream_ptr):
+        return _bcheck(self.handle, _lib.vfs_batch_set_stream(self.handle, stream_ptr))
+
+    def vfs_batch_set_problem(self, i, case):
+        k = _Keep()
+        nx, ny = self.sizes[i]
+        nn = (nx + 1) * (ny + 1)
+        fs = [(nx + 1) * ny, nx * (ny + 1)]
+        ubc = case.get("u_bc")
+        g = (ctypes.c_double * 3)(*((list(case["g"]) + [0.0] * 3)[:3]))
+        return _bcheck(self.handle, _lib.vfs_batch_set_problem(
+            self.handle, i, k.ptr(case["phi_l"], nn), k.ptr(case.get("phi_s"), nn),
+            k.ptr(case["rho"], nx * ny), k.ptr(case["mu"], nx * ny),
+            k.ptr(case["u"][0], fs[0]), k.ptr(case["u"][1], fs[1]),
+            k.ptr(ubc[0], fs[0]) if ubc is not None else None,
+            k.ptr(ubc[1], fs[1]) if ubc is not None else None, ctypes.cast(g, _P)))
+
+    def vfs_batch_set_solver(self, rel_tol=1e-6, max_iter=200000, w_min=1e-3):
+        return _bcheck(self.handle, _lib.vfs_batch_set_solver(self.handle, rel_tol, max_iter, w_min))
+
+    def vfs_batch_set_tiles(self, variant, blocks_per_cu):
+        return _bcheck(self.handle, _lib.vfs_batch_set_tiles(self.handle, variant, blocks_per_cu))
+
+    def vfs_batch_time_variant(self, variant, blocks_per_cu, iterations=50):
+        ms = _D()
+        _bcheck(self.handle, _lib.vfs_batch_time_variant(self.handle, variant, blocks_per_cu,
+                                                         iterations, ctypes.byref(ms)))
+        return ms.value
+
+    def vfs_batch_step(self, dt, allow_unconverged=False):
+        allow = (VFS_OK, VFS_ENOTCONV) if allow_unconverged else (VFS_OK,)
+        return _bcheck(self.handle, _lib.vfs_batch_step(self.handle, dt), allow)
+
+    def vfs_batch_get_velocity(self, i):
+        nx, ny = self.sizes[i]
+        u = np.zeros((nx + 1) * ny)
+        v = np.zeros(nx * (ny + 1))
+        _bcheck(self.handle, _lib.vfs_batch_get_velocity(self.handle, i, u.ctypes.data, v.ctypes.data))
+        return [u.reshape((nx + 1, ny), order="F"), v.reshape((nx, ny + 1), order="F")]
+
+    def vfs_batch_get_solution(self, i):
+        nx, ny = self.sizes[i]
+        x = np.zeros(2 * nx * ny + (nx + 1) * (ny + 1))
+        _bcheck(self.handle, _lib.vfs_batch_get_solution(self.handle, i, x.ctypes.data))
+        return x
+
+    def vfs_batch_get_problem(self, i):
+        it, ps = _I(), _I()
+        rel, lat = _D(), _D()
+        na = ctypes.c_int64()
+        _bcheck(self.handle, _lib.vfs_batch_get_problem(self.handle, i, ctypes.byref(it), ctypes.byref(ps),
+                                                        ctypes.byref(rel), ctypes.byref(lat),
+                                                        ctypes.byref(na)))
+        return dict(iterations=it.value, passes=ps.value, rel_residual=rel.value,
+                    latency_ms=lat.value, n_active=na.value)
+
+    def vfs_batch_get_stats(self):
+        st = vfs_batch_stats()
+        _bcheck(self.handle, _lib.vfs_batch_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+
+def batch_from_cases(case_list, tol=1e-6, max_iter=200000, w_min=1e-3):
+    b = Batch([c["n"] for c in case_list], [c["h"] for c in case_list])
+    for i, c in enumerate(case_list):
+        b.vfs_batch_set_problem(i, c)
+    b.vfs_batch_set_solver(tol, max_iter, w_min)
+    return b
