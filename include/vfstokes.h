@@ -58,7 +58,8 @@ extern "C" {
 /* preconditioners */
 #define VFS_PRECOND_NONE     0
 #define VFS_PRECOND_JACOBI   1   /* diagonal of A */
-#define VFS_PRECOND_LEARNED  3   /* U-Net correction inside flexible CG */
+#define VFS_PRECOND_LEARNED  3   /* U-Net correction inside flexible CG (3D, VFS_MIXED;
+                                    attach a network with vfs_set_preconditioner) */
 
 /* arithmetic of the solve */
 #define VFS_FP64   0   /* FP64 vectors, coefficients, apply and reductions */
@@ -100,6 +101,13 @@ typedef struct vfs_stats {
     double  t_update_avg_ms;
     int64_t n_apply_timed;
     int64_t n_update_timed;
+    /* learned preconditioner (VFS_PRECOND_LEARNED): average device time of
+       one network application (scale, pack, forward, unpack) under
+       profiling, and the number of iterations whose network direction was
+       not a descent direction and was replaced by the Jacobi one */
+    double  t_precond_avg_ms;
+    int32_t precond_fallbacks;
+    int32_t pad0;
 } vfs_stats;
 
 /* Last error message of a context (or of the failed create when ctx is NULL). */
@@ -185,12 +193,12 @@ int vfs_set_profiling(vfs_ctx* ctx, int on);
 int vfs_get_sizes(const vfs_ctx* ctx, int64_t* n_samples, int64_t* n_faces);
 
 /* ------------------------------------------------------------------------
- * Batched 2D steps: many independent problems of different sizes.  Their
- * CG solves run in one persistent launch per refinement pass (FP32 Jacobi
- * PCG with FP64 reductions inside, FP64 residual and refinement between
- * passes); each pass is captured once in a hipGraph and replayed.  Every
- * problem is a full step of the method above (same equations, inputs and
- * outputs as a single context), always in VFS_MIXED arithmetic.
+ * Batched 2D steps: many independent problems of different sizes.  All
+ * their solves run in one persistent launch (FP32 Jacobi PCG with FP64
+ * reductions, FP64 residual and iterative refinement per problem, each
+ * problem retiring on its own), captured once in a hipGraph and replayed.
+ * Every problem is a full step of the method above (same equations, inputs
+ * and outputs as a single context), always in VFS_MIXED arithmetic.
  * ------------------------------------------------------------------------ */
 typedef struct vfs_batch vfs_batch;
 
@@ -242,6 +250,72 @@ int vfs_batch_get_solution(vfs_batch* b, int i, double* x);   /* sample order */
 int vfs_batch_get_problem(vfs_batch* b, int i, int* iterations, int* passes,
                           double* rel_residual, double* latency_ms, int64_t* n_active);
 int vfs_batch_get_stats(vfs_batch* b, vfs_batch_stats* out);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner (3D).  Not part of the paper, whose CG uses an
+ * algebraic Schwarz preconditioner (Section 8 end, Section 9): a U-Net
+ * style network (Ronneberger et al. 2015) maps a residual r to a correction
+ * z inside flexible CG (Golub and Ye 1999, Notay 2000; Polak-Ribiere beta),
+ * with the Jacobi direction D^-1 r whenever z is not a descent direction.
+ *
+ * Network: 3x3x3 convolutions, no biases, ReLU, 2x2x2 mean pooling,
+ * nearest upsampling, additive skips.  Layers (Cin -> Cout, level):
+ *   enc0 16->16 L0, enc1 16->32 L1, enc2 32->64 L2, enc3 64->128 L3,
+ *   bott 128->64 L3, dec2 64->32 L2, dec1 32->16 L1, dec0 16->6 L0
+ *   c0 = relu(enc0(x)); c1 = relu(enc1(pool c0)); c2 = relu(enc2(pool c1));
+ *   c3 = relu(enc3(pool c2)); d3 = relu(bott(c3));
+ *   d2 = relu(dec2(up d3 + c2)); d1 = relu(dec1(up d2 + c1));
+ *   y = dec0(up d1 + c0)
+ * BF16 storage and MFMA operands, FP32 accumulation, FP32 master weights.
+ * Weights: FP32, layers in the order above, each [Cout][Cin][dz][dy][dx]
+ * (C order), out[z,y,x,co] = sum W[co,ci,dz,dy,dx] in[z+dz-1, y+dy-1, x+dx-1, ci]
+ * with zero padding; vfs_unet_param_count() values in total.
+ * Tensors at this boundary: FP32, dense, [Z][Y][X][C] (C fastest); X, Y, Z
+ * positive multiples of 8.  Input C = 16, output C = 6.
+ * Solver coupling: a grid of n cells uses extents roundup(n_a + 1, 8); input
+ * channel q < 6 at voxel (i, j, k) is s sqrt(D^-1) r of sample set q
+ * (p, txx, tyy, txy, txz, tyz) at index (i, j, k), s = sqrt(n_active) /
+ * ||sqrt(D^-1) r||; channels 8, 9, 10 hold the cell's W_L, W_F and
+ * log10(1 + dt mu / (rho h^2)) / 6; the others are 0.  The correction is
+ * z = sqrt(D^-1) y / s on active samples.
+ * ------------------------------------------------------------------------ */
+typedef struct vfs_unet vfs_unet;
+const char* vfs_unet_last_error(const vfs_unet* u);
+int64_t vfs_unet_param_count(void);
+/* New network with zero weights (set them before use). */
+int vfs_unet_create(vfs_unet** out);
+int vfs_unet_destroy(vfs_unet* u);
+/* Stream for the network's work (must equal the stream of any context it
+ * is used with). */
+int vfs_unet_set_stream(vfs_unet* u, void* hip_stream);
+/* Replace the FP32 master weights (count = vfs_unet_param_count(), host or
+ * device); resets the Adam state and the gradient.  EINVAL on NaN/Inf. */
+int vfs_unet_set_weights(vfs_unet* u, const float* w, int64_t count);
+int vfs_unet_get_weights(vfs_unet* u, float* w, int64_t count);
+/* Accumulated weight gradient (same layout as the weights). */
+int vfs_unet_get_grad(vfs_unet* u, float* g, int64_t count);
+int vfs_unet_zero_grad(vfs_unet* u);
+/* y = network(x); keeps the activations for vfs_unet_backward. */
+int vfs_unet_forward(vfs_unet* u, int X, int Y, int Z, const float* x, float* y);
+/* Adds the gradient of <gy, y> with respect to the weights (chain rule
+ * through the last forward) to the accumulated gradient.  ESTATE without a
+ * preceding forward. */
+int vfs_unet_backward(vfs_unet* u, const float* gy);
+/* Adam (Kingma and Ba 2015, bias-corrected) on the weights with gradient
+ * grad_scale * (accumulated gradient); clears the accumulated gradient. */
+int vfs_unet_adam(vfs_unet* u, double lr, double beta1, double beta2, double eps,
+                  double grad_scale);
+/* One training sample on an assembled 3D context: network correction f of
+ * the residual r (sample order; A e = r, e the exact correction), loss
+ * L = 1 - (f.r)^2 / ((f.A f)(e.r)) (the A-norm error left after an exact
+ * line search along f, relative to that of e), and its gradient added to
+ * the accumulated weight gradient.  *loss receives L. */
+int vfs_unet_train_step(vfs_unet* u, vfs_ctx* ctx, const double* r, const double* e,
+                        double* loss);
+/* Attach a network (not owned; NULL detaches) for VFS_PRECOND_LEARNED. */
+int vfs_set_preconditioner(vfs_ctx* ctx, vfs_unet* u);
+/* z = network correction of r on the assembled context (sample order). */
+int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z);
 
 #ifdef __cplusplus
 }

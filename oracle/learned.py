@@ -19,6 +19,14 @@ each piece below is written from its published definition:
   to e.  Its gradient is  dL/df = (2a / (b E)) ((a / b) A f - r)  with
   a = f.r, b = f.A f, E = e.r.
 * Adam (Kingma and Ba 2015) with bias correction.
+* The preconditioner is a two-level step in the manner of multigrid: a
+  Jacobi step with exact line search, d = D^-1 r, a1 = r.d / d.A d,
+  smooths the residual to r1 = r - a1 A d; the network maps r1 to a
+  direction n, used with an exact line search w = n.r1 / n.A n; the result
+  is z = a1 d + w n.  The line searches make the step independent of the
+  network's output scale, and the network only has to supply the smooth
+  part of the error that the Jacobi step leaves.  Training pairs are
+  transformed the same way: (r, e) -> (r1, e1 = e - a1 d), A e1 = r1.
 * Flexible CG with the Polak-Ribiere form of beta (Golub and Ye 1999;
   Notay 2000), so that a non-linear preconditioner can be used; a direction
   that is not a descent direction (z.r <= 0 or not finite) is replaced by
@@ -59,9 +67,9 @@ LAYERS = (
     ("dec1", 32, 16, 1, True),
     ("dec0", 16, 6, 0, False),
 )
-N_IN = 16          # input channels: 6 residual sets + 3 geometry + 7 zero
+N_IN = 16          # input channels: 6 residual sets, 2 zero, 3 geometry, 5 zero
 N_OUT = 6          # one correction channel per 3D sample set
-GEOM = (6, 7, 8)   # W_L(cell), W_F(cell), log10(1 + dt mu / (rho h^2)) / 6
+GEOM = (8, 9, 10)  # W_L(cell), W_F(cell), log10(1 + dt mu / (rho h^2)) / 6
 
 
 def layer_sizes():
@@ -238,7 +246,7 @@ def pack_input(asm, case, r_full, dinv_full):
     """Network input (Z, Y, X, 16) of a residual r (sample order, FP64) and
     the scale s: channel q at voxel (i, j, k) is s * sqrt(D^-1) r of set q's
     sample (i, j, k) (0 for inactive samples), with s = sqrt(n_active) /
-    ||sqrt(D^-1) r|| (0 if that norm is 0); channels 6-8 hold geometry."""
+    ||sqrt(D^-1) r|| (0 if that norm is 0); channels 8-10 hold geometry."""
     g = asm.grid
     Z, Y, X = tensor_dims(g.n)
     act = asm.active.astype(np.float64)
@@ -299,6 +307,35 @@ def loss_and_grad(apply_A, f, r, e):
     L = 1.0 - a * a / (b * E)
     g = (2.0 * a / (b * E)) * ((a / b) * q - r)
     return L, g
+
+
+# ------------------------------------------------------- two-level step
+def smooth(apply_A, dinv, r):
+    """Jacobi step with exact line search: (a1, d, A d, r1 = r - a1 A d)."""
+    d = dinv * r
+    qd = apply_A(d)
+    dq = float(d @ qd)
+    a1 = float(r @ d) / dq if dq > 0.0 else 0.0
+    return a1, d, qd, r - a1 * qd
+
+
+def smooth_pair(apply_A, dinv, r, e):
+    """Training pair after the Jacobi step: (r1, e1) with A e1 = r1."""
+    a1, d, qd, r1 = smooth(apply_A, dinv, r)
+    return r1, e - a1 * d
+
+
+def two_level(apply_A, dinv, r, net):
+    """z = a1 d + w n with n = net(r1) and w = n.r1 / n.A n (w = 0 when
+    n.A n <= 0 or a value is not finite)."""
+    a1, d, qd, r1 = smooth(apply_A, dinv, r)
+    n = net(r1)
+    qn = apply_A(n)
+    nq = float(n @ qn)
+    w = float(n @ r1) / nq if nq > 0.0 and np.isfinite(nq) else 0.0
+    if not np.isfinite(w):
+        w = 0.0
+    return a1 * d + w * n
 
 
 # ------------------------------------------------------------------ Adam

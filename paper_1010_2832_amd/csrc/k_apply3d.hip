@@ -47,11 +47,18 @@ struct Loader {
     const T* a;
     T beta;
     bool first;
+    bool fb;   // MODE_FDIR: use the Jacobi z instead of zs
 
-    // value of slice s at offset os (direction update in MODE_DIR)
+    // value of slice s at offset os (direction update in MODE_DIR / MODE_FDIR)
     __device__ __forceinline__ T value(long long os, bool own) const {
-        if (MODE == MODE_DIR) {
+        if (MODE == MODE_JDIR) {
             const T z = ZIN ? zs[os] : dinv[os] * r[os];
+            if (own && pout) pout[os] = z;
+            return z;
+        }
+        if (MODE == MODE_DIR || MODE == MODE_FDIR) {
+            const T z = (MODE == MODE_FDIR) ? (fb ? dinv[os] * r[os] : zs[os])
+                                            : (ZIN ? zs[os] : dinv[os] * r[os]);
             const T val = first ? z : z + beta * pin[os];
             if (own) pout[os] = val;
             return val;
@@ -69,11 +76,19 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
                                                 const T* __restrict__ c, const T* __restrict__ K,
                                                 const T* __restrict__ bv, RedArgs ra) {
     T beta = T(0);
-    bool first = true;
+    bool first = true, fb = false;
     if (MODE == MODE_DIR) {
         if (ra.sc->done) return;
         double bd;
         if (!cg_direction_preamble<NT>(ra, blockIdx.x, bd)) return;
+        first = ra.kidx == 0;
+        beta = (T)bd;
+    } else if (MODE == MODE_JDIR) {
+        if (ra.skip && *ra.skip) return;
+    } else if (MODE == MODE_FDIR) {
+        if (ra.sc->done) return;
+        double bd;
+        if (!fcg_direction_preamble<NT>(ra, blockIdx.x, bd, fb)) return;
         first = ra.kidx == 0;
         beta = (T)bd;
     }
@@ -84,7 +99,7 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
     const long long NP = g.NP;
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
-    Loader<T, MODE, ZIN> ld{g, r, zs, dinv, pin, pout, a, beta, first};
+    Loader<T, MODE, ZIN> ld{g, r, zs, dinv, pin, pout, a, beta, first, fb};
     double acc = 0.0;
   for (int wtile = blockIdx.x; wtile < tl.count; wtile += gridDim.x) {
     int i0, j0, k0;
@@ -236,7 +251,8 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
 #pragma unroll
                 for (int s = 0; s < 6; ++s) {
                     q[s * NP + o] = y[s];
-                    if (MODE == MODE_DIR) acc += (double)vcur[s] * (double)y[s];
+                    if (MODE == MODE_DIR || MODE == MODE_FDIR || MODE == MODE_JDIR)
+                        acc += (double)vcur[s] * (double)y[s];
                 }
             }
         }
@@ -377,6 +393,16 @@ void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* 
         else
             hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                                dinv, pin, pout, q, a, c, K, bvec, ra);
+    } else if (mode == MODE_FDIR) {
+        hipLaunchKernelGGL((k_apply3d<T, MODE_FDIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
+                           dinv, pin, pout, q, a, c, K, bvec, ra);
+    } else if (mode == MODE_JDIR) {
+        if (zin)
+            hipLaunchKernelGGL((k_apply3d<T, MODE_JDIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
+                               dinv, pin, pout, q, a, c, K, bvec, ra);
+        else
+            hipLaunchKernelGGL((k_apply3d<T, MODE_JDIR, false>), gs, dim3(NT), 0, s, g, tl, r,
+                               zsrc, dinv, pin, pout, q, a, c, K, bvec, ra);
     } else if (mode == MODE_APPLY) {
         hipLaunchKernelGGL((k_apply3d<T, MODE_APPLY, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                            dinv, pin, pout, q, a, c, K, bvec, ra);

@@ -298,6 +298,7 @@ __global__ __launch_bounds__(NT) void k_cg_init(long long n, const T* bsrc, T* _
         sc->tol2 = tol * tol;
         sc->max_iter = max_iter;
         sc->alpha = sc->beta = sc->pq = 0.0;
+        sc->fallbacks = 0;
     }
     double vv[2] = {rz, rr};
     block_partial<2, NT>(vv, part_out, gridDim.x, blockIdx.x);
@@ -412,10 +413,12 @@ void launch_apply(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r,
     } else if (mode == MODE_APPLY) {
         hipLaunchKernelGGL((k_apply2d<T, MODE_APPLY, false>), gs, dim3(NT), 0, s, g, r, zsrc, dinv,
                            pin, pout, q, a, c, K, bvec, ra);
-    } else {
+    } else if (mode == MODE_RESID) {
         hipLaunchKernelGGL((k_apply2d<T, MODE_RESID, false>), gs, dim3(NT), 0, s, g, r, zsrc, dinv,
                            pin, pout, q, a, c, K, bvec, ra);
     }
+    // MODE_FDIR exists in 3D only (the learned preconditioner is 3D); the
+    // host never requests it for a 2D grid
 }
 
 template <typename T>

@@ -8,6 +8,7 @@
 #include <string>
 
 #include "vfs_internal.h"
+#include "vfs_unet.h"
 
 using namespace vfs;
 
@@ -177,6 +178,56 @@ int run_chunks(vfs_ctx* ctx, Vecs<T>& v, bool set_bb, Scalars* out) {
     }
 }
 
+// Flexible CG iterations with the learned two-level preconditioner (3D,
+// FP32): z = a1 D^-1 r + w network(r1) from the (r.D^-1 r, r.r) partials
+// of the previous kernel (net_precond), then the direction (MODE_FDIR: z or
+// the Jacobi z, Polak-Ribiere beta) + apply, then the update.  Every launch
+// after a stop sees sc->done and does nothing.
+int run_chunks_fcg(vfs_ctx* ctx, Vecs<float>& v, bool set_bb, Scalars* out) {
+    const Geo& g = ctx->g;
+    const Parts P = parts(ctx);
+    vfs_unet* u = ctx->net;
+    hipStream_t s = ctx->stream;
+    const int nbA = apply_blocks(g, ctx->tiles), nbU = update_blocks(g, ctx->tiles);
+    const int nbV = vec_grid_blocks(g), nbZ = coarse_blocks(g);
+    const int* skip = &ctx->sc->done;
+    int chunk = 4;
+    int kidx = 0;
+    for (;;) {
+        for (int k = 0; k < chunk; ++k, ++kidx) {
+            float* pin = (kidx & 1) ? v.p1 : v.p0;
+            float* pout = (kidx & 1) ? v.p0 : v.p1;
+            const int nb2 = kidx == 0 ? nbV : nbU;
+            const bool timed = ctx->prof && k == 0;
+            if (timed) HIPCHK(hipEventRecord(ctx->pev[3], s));
+            int rc = net_precond(u, ctx, v.r, v.dinv, v.a, v.c, v.K, P.B, nb2, v.q, skip);
+            if (rc) return fail(ctx, rc, u->err);
+            const RedArgs ra{ctx->sc, net_region(ctx, 4), nbZ, P.A, kidx,
+                             (set_bb && kidx == 0) ? 1 : 0, P.B, nb2};
+            const RedArgs rb{ctx->sc, P.A, nbA, P.B, kidx, 0};
+            if (timed) HIPCHK(hipEventRecord(ctx->pev[0], s));
+            launch_apply<float>(g, ctx->tiles, MODE_FDIR, false, v.r, ctx->z32, v.dinv, pin, pout,
+                                v.q, v.a, v.c, v.K, nullptr, ra, s);
+            if (timed) HIPCHK(hipEventRecord(ctx->pev[1], s));
+            launch_update<float>(g, ctx->tiles, v.x, pout, v.r, v.q, v.dinv, nullptr, rb, s);
+            if (timed) HIPCHK(hipEventRecord(ctx->pev[2], s));
+        }
+        HIPCHK(hipGetLastError());
+        int rc = read_scalars(ctx, 0, out);
+        if (rc) return rc;
+        const int kidx0 = kidx - chunk;
+        if (ctx->prof && (!out->done || out->iter > kidx0)) {
+            ctx->prof_apply_ms += elapsed(ctx->pev[0], ctx->pev[1]);
+            ctx->prof_update_ms += elapsed(ctx->pev[1], ctx->pev[2]);
+            ctx->prof_precond_ms += elapsed(ctx->pev[3], ctx->pev[0]);
+            ++ctx->prof_apply_n;
+            ++ctx->prof_update_n;
+        }
+        if (out->done) return VFS_OK;
+        chunk = std::min(chunk * 2, 64);
+    }
+}
+
 // r = b - A x in FP64 and ||r||^2 -> sc[1].aux0 (host copy in *so)
 int true_residual(vfs_ctx* ctx, const double* b, const double* x, Scalars* so) {
     const Geo& g = ctx->g;
@@ -260,6 +311,15 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
     Vecs<float> v{ctx->x32, ctx->r32, ctx->p032, ctx->p132, ctx->q32, nullptr, ctx->a32, ctx->c32,
                   ctx->K32, ctx->dinv32};
     if (int rc0 = zero_dirs(ctx, true)) return rc0;
+    const bool learned = ctx->precond == VFS_PRECOND_LEARNED;
+    if (learned) {
+        if (!ctx->net) return fail(ctx, VFS_ESTATE, "no preconditioner network attached");
+        if (!ctx->net->have_weights) return fail(ctx, VFS_ESTATE, "the network has no weights");
+        if (ctx->net->stream != ctx->stream)
+            return fail(ctx, VFS_EINVAL, "network and context must use the same stream");
+        if (int rc0 = net_prepare_ctx(ctx->net, ctx)) return fail(ctx, rc0, ctx->net->err);
+    }
+    int fallbacks = 0;
     HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), ctx->stream));
     Scalars so{};
     int rc = true_residual(ctx, b, x, &so);
@@ -281,9 +341,10 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
                               ctx->max_iter - total, ctx->sc, P.B, ctx->stream);
         HIPCHK(hipGetLastError());
         Scalars s{};
-        rc = run_chunks<float>(ctx, v, true, &s);
+        rc = learned ? run_chunks_fcg(ctx, v, true, &s) : run_chunks<float>(ctx, v, true, &s);
         if (rc) return rc;
         total += s.iter;
+        fallbacks += s.fallbacks;
         launch_axpy_f32_to_f64(g, x, ctx->x32, ctx->sc + 1, ctx->stream);
         rc = true_residual(ctx, b, x, &so);
         if (rc) return rc;
@@ -301,6 +362,7 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
         }
         rho = rho_new;
     }
+    ctx->stats.precond_fallbacks = fallbacks;
     ctx->stats.iterations = total;
     ctx->stats.outer_iterations = outer;
     ctx->stats.rel_residual = rel;
@@ -421,6 +483,13 @@ namespace vfs {
 
 int ctx_assemble(vfs_ctx* ctx, double dt) { return assemble_internal(ctx, dt); }
 int ctx_recover(vfs_ctx* ctx) { return recover_internal(ctx); }
+int ctx_put_samples(vfs_ctx* ctx, const double* user, double* dst) {
+    return pack_samples(ctx, user, dst);
+}
+int ctx_get_samples(vfs_ctx* ctx, const double* src, double* user) {
+    return unpack_samples(ctx, src, user);
+}
+int ctx_fail(vfs_ctx* ctx, int code, const std::string& msg) { return fail(ctx, code, msg); }
 
 Geo make_geo(int dim, int nx, int ny, int nz, double h) {
     Geo g{};
@@ -476,7 +545,7 @@ int vfs_destroy(vfs_ctx* ctx) {
                     ctx->K32,   ctx->a32,   ctx->c32,  ctx->dinv32, ctx->x,      ctx->r,
                     ctx->p0,    ctx->p1,    ctx->q,    ctx->z,      ctx->x32,    ctx->r32,
                     ctx->p032,  ctx->p132,  ctx->q32,  ctx->z32,    ctx->partials, ctx->counter,
-                    ctx->sc,    ctx->flag,  ctx->stage};
+                    ctx->sc,    ctx->flag,  ctx->stage, ctx->netvec, ctx->netpart, ctx->netcoef};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->tile_flags) (void)hipFree(ctx->tile_flags);
@@ -683,10 +752,12 @@ int vfs_set_gravity(vfs_ctx* ctx, const double* g) {
 int vfs_set_solver(vfs_ctx* ctx, int precond, int precision, double rel_tol, int max_iter,
                    double w_min) {
     if (!ctx) return VFS_EINVAL;
-    if (precond != VFS_PRECOND_JACOBI)
+    if (precond != VFS_PRECOND_JACOBI && precond != VFS_PRECOND_LEARNED)
         return fail(ctx, VFS_EINVAL, "unsupported preconditioner");
     if (precision != VFS_FP64 && precision != VFS_MIXED)
         return fail(ctx, VFS_EINVAL, "precision must be VFS_FP64 or VFS_MIXED");
+    if (precond == VFS_PRECOND_LEARNED && (ctx->g.dim != 3 || precision != VFS_MIXED))
+        return fail(ctx, VFS_EINVAL, "the learned preconditioner needs a 3D grid and VFS_MIXED");
     if (!(rel_tol > 0.0) || !(rel_tol < 1.0)) return fail(ctx, VFS_EINVAL, "rel_tol must be in (0,1)");
     if (max_iter < 1) return fail(ctx, VFS_EINVAL, "max_iter must be >= 1");
     if (!(w_min >= 0.0) || !(w_min < 0.5)) return fail(ctx, VFS_EINVAL, "w_min must be in [0,0.5)");
@@ -850,6 +921,8 @@ int vfs_get_stats(vfs_ctx* ctx, vfs_stats* out) {
     ctx->stats.t_apply_avg_ms = ctx->prof_apply_n ? ctx->prof_apply_ms / ctx->prof_apply_n : 0.0;
     ctx->stats.t_update_avg_ms =
         ctx->prof_update_n ? ctx->prof_update_ms / ctx->prof_update_n : 0.0;
+    ctx->stats.t_precond_avg_ms =
+        ctx->prof_apply_n ? ctx->prof_precond_ms / ctx->prof_apply_n : 0.0;
     *out = ctx->stats;
     return VFS_OK;
 }
@@ -858,7 +931,7 @@ int vfs_set_profiling(vfs_ctx* ctx, int on) {
     if (!ctx) return VFS_EINVAL;
     ctx->prof = on != 0;
     if (ctx->prof) {
-        ctx->prof_apply_ms = ctx->prof_update_ms = 0.0;
+        ctx->prof_apply_ms = ctx->prof_update_ms = ctx->prof_precond_ms = 0.0;
         ctx->prof_apply_n = ctx->prof_update_n = 0;
     }
     return VFS_OK;

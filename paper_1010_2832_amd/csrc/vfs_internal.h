@@ -78,7 +78,8 @@ struct Scalars {
     int done;           // 0 running, 1 converged, 2 max_iter, 3 breakdown
     int flexible;
     long long n_active;
-    int pad[4];
+    int fallbacks;      // flexible CG: iterations that used the Jacobi direction
+    int pad[3];
 };
 
 // Partial-sum plumbing of one reduction-carrying launch.
@@ -89,6 +90,9 @@ struct RedArgs {
     double* part_out;        // this kernel's partials (one per workgroup)
     int kidx;                // CG iteration index within the current run
     int set_bb;              // first iteration of a fresh solve: bb := r.r
+    const double* part_in2;  // flexible CG: (r.D^-1 r, r.r) partials of the update
+    int nb_in2;
+    const int* skip;         // MODE_JDIR: the launch does nothing if *skip != 0
 };
 
 // Compacted list of active 3D tiles (64 x 4 anchors in x,y times 8 planes
@@ -179,11 +183,18 @@ struct vfs_ctx {
 
     bool assembled = false;
     double dt_assembled = 0.0;
+
+    // learned preconditioner (not owned) and its work space: 5 FP32 sample
+    // vectors (d, A d, r1, n, A n), partial regions, line-search coefficients
+    struct vfs_unet* net = nullptr;
+    float* netvec = nullptr;
+    double* netpart = nullptr;
+    double* netcoef = nullptr;
     vfs_stats stats{};
     hipEvent_t ev[6] = {};
     bool prof = false;
     hipEvent_t pev[4] = {};
-    double prof_apply_ms = 0.0, prof_update_ms = 0.0;
+    double prof_apply_ms = 0.0, prof_update_ms = 0.0, prof_precond_ms = 0.0;
     long long prof_apply_n = 0, prof_update_n = 0;
 };
 
@@ -232,7 +243,11 @@ void launch_to_f32(const double* src, float* dst, long long n, hipStream_t s);
 void launch_mask(double* dst, const double* src, const double* a, long long n, hipStream_t s);
 
 // CG building blocks (k_pcg.hip); T = double or float
-enum ApplyMode { MODE_DIR = 0, MODE_APPLY = 1, MODE_RESID = 2 };
+// MODE_FDIR: flexible-CG direction from a given z (or the Jacobi z when the
+// given one is not a descent direction) with the Polak-Ribiere beta.
+// MODE_JDIR: v = D^-1 r (or a given vector), stored to pout if set, q = A v,
+// partials of v.q; no CG scalars are touched.
+enum ApplyMode { MODE_DIR = 0, MODE_APPLY = 1, MODE_RESID = 2, MODE_FDIR = 3, MODE_JDIR = 4 };
 int apply_grid_blocks(const Geo& g);   // 2D apply grid / all 3D tiles (capacity)
 int vec_grid_blocks(const Geo& g);     // dense pointwise kernels
 // workgroups of one apply / update launch (the partial count they write)

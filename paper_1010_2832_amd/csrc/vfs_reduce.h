@@ -172,4 +172,44 @@ __device__ __forceinline__ bool cg_direction_preamble(const RedArgs& ra, int bid
     return stop == 0;
 }
 
+// Preamble of a flexible-CG direction (Golub-Ye / Notay flexible CG with the
+// Polak-Ribiere beta).  Inputs: partials (z.r, z.q_prev, r.D^-1 q_prev) of
+// the preconditioner output z and partials (r.D^-1 r, r.r) of the update.
+// When z is not a descent direction (z.r <= 0 or non-finite) the Jacobi
+// direction D^-1 r is used instead (fb = true).  With r_k = r_{k-1} -
+// alpha q_{k-1}, beta = z_k.(r_k - r_{k-1}) / (z_{k-1}.r_{k-1})
+//                     = -alpha_{k-1} (z_k.q_{k-1}) / (z_{k-1}.r_{k-1}).
+template <int NT>
+__device__ __forceinline__ bool fcg_direction_preamble(const RedArgs& ra, int bid, double& beta,
+                                                       bool& fb) {
+    Scalars* sc = ra.sc;
+    double t3[3], t2[2];
+    reduce_partials<3, NT>(ra.part_in, ra.nb_in, t3);
+    reduce_partials<2, NT>(ra.part_in2, ra.nb_in2, t2);
+    const double zr = t3[0], zq = t3[1], rdq = t3[2], rdr = t2[0], rr = t2[1];
+    fb = !(zr > 0.0) || !isfinite(zr) || (ra.kidx > 0 && !isfinite(zq));
+    const double rz = fb ? rdr : zr;
+    const double bb = ra.set_bb ? rr : sc->bb;
+    int stop = 0;
+    if (!isfinite(rdr) || !isfinite(rr))
+        stop = 3;
+    else if (rr <= sc->tol2 * bb)
+        stop = 1;
+    else if (ra.kidx >= sc->max_iter)
+        stop = 2;
+    beta = ra.kidx == 0 ? 0.0 : -sc->alpha * (fb ? rdq : zq) / sc->rz[(ra.kidx + 1) & 1];
+    if (bid == 0 && threadIdx.x == 0) {
+        sc->rz[ra.kidx & 1] = rz;
+        sc->rr = rr;
+        sc->beta = beta;
+        if (ra.set_bb) sc->bb = bb;
+        if (fb && !stop) sc->fallbacks += 1;
+        if (stop) {
+            sc->done = stop;
+            sc->iter = ra.kidx;
+        }
+    }
+    return stop == 0;
+}
+
 }  // namespace vfs

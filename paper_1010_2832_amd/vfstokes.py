@@ -36,10 +36,12 @@ class vfs_stats(ctypes.Structure):
                 ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_recover_ms", ctypes.c_double), ("t_step_ms", ctypes.c_double),
                 ("t_apply_avg_ms", ctypes.c_double), ("t_update_avg_ms", ctypes.c_double),
-                ("n_apply_timed", ctypes.c_int64), ("n_update_timed", ctypes.c_int64)]
+                ("n_apply_timed", ctypes.c_int64), ("n_update_timed", ctypes.c_int64),
+                ("t_precond_avg_ms", ctypes.c_double), ("precond_fallbacks", ctypes.c_int32),
+                ("pad0", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
 
 
 class vfs_batch_stats(ctypes.Structure):
@@ -120,6 +122,21 @@ _SIGS = {
     "vfs_batch_get_problem": ([_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_D),
                                ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)], _I),
     "vfs_batch_get_stats": ([_P, ctypes.POINTER(vfs_batch_stats)], _I),
+    "vfs_unet_last_error": ([_P], ctypes.c_char_p),
+    "vfs_unet_param_count": ([], ctypes.c_int64),
+    "vfs_unet_create": ([ctypes.POINTER(_P)], _I),
+    "vfs_unet_destroy": ([_P], _I),
+    "vfs_unet_set_stream": ([_P, _P], _I),
+    "vfs_unet_set_weights": ([_P, _P, ctypes.c_int64], _I),
+    "vfs_unet_get_weights": ([_P, _P, ctypes.c_int64], _I),
+    "vfs_unet_get_grad": ([_P, _P, ctypes.c_int64], _I),
+    "vfs_unet_zero_grad": ([_P], _I),
+    "vfs_unet_forward": ([_P, _I, _I, _I, _P, _P], _I),
+    "vfs_unet_backward": ([_P, _P], _I),
+    "vfs_unet_adam": ([_P, _D, _D, _D, _D, _D], _I),
+    "vfs_unet_train_step": ([_P, _P, _P, _P, ctypes.POINTER(_D)], _I),
+    "vfs_set_preconditioner": ([_P, _P], _I),
+    "vfs_precond_apply": ([_P, _P, _P], _I),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -175,6 +192,23 @@ class _Keep:
             raise ValueError(f"expected {n} values, got {flat.size}")
         self.items.append(flat)
         return flat.ctypes.data
+
+
+def _ptr32(keep, arr, n):
+    """float32 buffer pointer: torch float32 tensors by pointer, anything
+    else converted to a contiguous float32 NumPy array (C order)."""
+    if _is_torch(arr):
+        import torch
+        if arr.dtype != torch.float32 or not arr.is_contiguous():
+            raise ValueError("torch tensors must be contiguous float32")
+        if arr.numel() != n:
+            raise ValueError(f"expected {n} values, got {arr.numel()}")
+        return arr.data_ptr()
+    flat = np.ascontiguousarray(np.asarray(arr, dtype=np.float32).ravel())
+    if flat.size != n:
+        raise ValueError(f"expected {n} values, got {flat.size}")
+    keep.items.append(flat)
+    return flat.ctypes.data
 
 
 def _check(ctx, rc, allow=(VFS_OK,)):
@@ -280,8 +314,10 @@ class Context:
 
     def vfs_set_solver(self, precond=VFS_PRECOND_JACOBI, precision=VFS_FP64, rel_tol=1e-6,
                        max_iter=100000, w_min=1e-3):
-        return _check(self.handle, _lib.vfs_set_solver(self.handle, precond, precision, rel_tol,
-                                                       max_iter, w_min))
+        rc = _check(self.handle, _lib.vfs_set_solver(self.handle, precond, precision, rel_tol,
+                                                     max_iter, w_min))
+        self._solver = (precond, precision, rel_tol, max_iter, w_min)
+        return rc
 
     # work ------------------------------------------------------------------
     def vfs_step(self, dt, allow_unconverged=False):
@@ -363,6 +399,19 @@ class Context:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(self.handle, _lib.vfs_get_sizes(self.handle, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    # learned preconditioner -------------------------------------------------
+    def vfs_set_preconditioner(self, net):
+        self._net = net   # the context does not own the network; keep it alive
+        return _check(self.handle, _lib.vfs_set_preconditioner(self.handle,
+                                                               net.handle if net else None))
+
+    def vfs_precond_apply(self, r):
+        k = _Keep()
+        n = self.n_samples()
+        z = np.zeros(n)
+        _check(self.handle, _lib.vfs_precond_apply(self.handle, k.ptr(r, n), z.ctypes.data))
+        return z
 
 
 def context_from_case(case, precision=VFS_FP64, tol=None, max_iter=200000, w_min=1e-3):
@@ -495,3 +544,87 @@ def batch_from_cases(case_list, tol=1e-6, max_iter=200000, w_min=1e-3):
         b.vfs_batch_set_problem(i, c)
     b.vfs_batch_set_solver(tol, max_iter, w_min)
     return b
+
+
+# ---------------------------------------------------------------------------
+# learned preconditioner network
+# ---------------------------------------------------------------------------
+def vfs_unet_param_count():
+    return int(_lib.vfs_unet_param_count())
+
+
+def _ucheck(u, rc, allow=(VFS_OK,)):
+    if rc not in allow:
+        raise VfsError(rc, _lib.vfs_unet_last_error(u).decode())
+    return rc
+
+
+class Unet:
+    """Owns one vfs_unet (weights, Adam state, activation tensors)."""
+
+    def __init__(self):
+        out = _P()
+        rc = _lib.vfs_unet_create(ctypes.byref(out))
+        if rc != VFS_OK:
+            raise VfsError(rc, _lib.vfs_unet_last_error(None).decode())
+        self.handle = out
+        self.n_params = vfs_unet_param_count()
+
+    def close(self):
+        if self.handle:
+            _lib.vfs_unet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def vfs_unet_set_stream(self, stream_ptr):
+        return _ucheck(self.handle, _lib.vfs_unet_set_stream(self.handle, stream_ptr))
+
+    def vfs_unet_set_weights(self, w):
+        k = _Keep()
+        return _ucheck(self.handle, _lib.vfs_unet_set_weights(
+            self.handle, _ptr32(k, w, self.n_params), self.n_params))
+
+    def vfs_unet_get_weights(self):
+        w = np.zeros(self.n_params, dtype=np.float32)
+        _ucheck(self.handle, _lib.vfs_unet_get_weights(self.handle, w.ctypes.data, self.n_params))
+        return w
+
+    def vfs_unet_get_grad(self):
+        g = np.zeros(self.n_params, dtype=np.float32)
+        _ucheck(self.handle, _lib.vfs_unet_get_grad(self.handle, g.ctypes.data, self.n_params))
+        return g
+
+    def vfs_unet_zero_grad(self):
+        return _ucheck(self.handle, _lib.vfs_unet_zero_grad(self.handle))
+
+    def vfs_unet_forward(self, x):
+        """x: (Z, Y, X, 16) float array; returns y (Z, Y, X, 6) float32."""
+        Z, Y, X = (int(q) for q in np.shape(x)[:3])
+        k = _Keep()
+        y = np.zeros((Z, Y, X, 6), dtype=np.float32)
+        _ucheck(self.handle, _lib.vfs_unet_forward(self.handle, X, Y, Z,
+                                                   _ptr32(k, x, Z * Y * X * 16), y.ctypes.data))
+        return y
+
+    def vfs_unet_backward(self, gy):
+        Z, Y, X = (int(q) for q in np.shape(gy)[:3])
+        k = _Keep()
+        return _ucheck(self.handle, _lib.vfs_unet_backward(self.handle,
+                                                           _ptr32(k, gy, Z * Y * X * 6)))
+
+    def vfs_unet_adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
+        return _ucheck(self.handle, _lib.vfs_unet_adam(self.handle, lr, beta1, beta2, eps,
+                                                       grad_scale))
+
+    def vfs_unet_train_step(self, ctx, r, e):
+        k = _Keep()
+        n = ctx.n_samples()
+        loss = _D()
+        _ucheck(self.handle, _lib.vfs_unet_train_step(self.handle, ctx.handle, k.ptr(r, n),
+                                                      k.ptr(e, n), ctypes.byref(loss)))
+        return loss.value

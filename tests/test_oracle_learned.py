@@ -168,8 +168,9 @@ def test_pack_unpack_of_identity_network_is_jacobi(small3d):
     assert np.isclose(np.sum(x[..., :6] ** 2), asm.active.sum())
     f = learned.unpack_output(asm, x[..., :6], dinv, s)
     assert np.allclose(f, dinv * r, rtol=1e-12, atol=0)
-    # geometry channels lie in [0, 1]
-    assert x[..., 6:9].min() >= 0.0 and x[..., 6:9].max() <= 1.0
+    # geometry channels lie in [0, 1]; the unused channels are zero
+    assert x[..., 8:11].min() >= 0.0 and x[..., 8:11].max() <= 1.0
+    assert not x[..., 6:8].any() and not x[..., 11:].any()
 
 
 def test_unpack_adjoint(small3d):
@@ -212,6 +213,39 @@ def test_loss_closed_forms_and_gradient(small3d):
     # f = 0 on the active samples: defined as no progress
     L, g = learned.loss_and_grad(apply_full, np.zeros_like(r), r, e)
     assert L == 1.0 and not g.any()
+
+
+def test_two_level_step_reductions(small3d):
+    """With the exact coarse correction the two-level step is the exact
+    inverse; with no network it is a multiple of the Jacobi direction; the
+    smoothed pair keeps A e1 = r1 and the Jacobi step never increases the
+    A-norm error."""
+    case, asm, dinv, apply_full, solve_full = small3d
+    rng = np.random.default_rng(15)
+    r = np.where(asm.active, rng.normal(size=asm.grid.n_samples()), 0.0)
+    e = solve_full(r)
+    z = learned.two_level(apply_full, dinv, r, solve_full)
+    assert np.linalg.norm(z - e) <= 1e-8 * np.linalg.norm(e)
+    z0 = learned.two_level(apply_full, dinv, r, lambda v: np.zeros_like(v))
+    a1 = (r @ (dinv * r)) / ((dinv * r) @ apply_full(dinv * r))
+    assert np.allclose(z0, a1 * dinv * r, rtol=1e-12, atol=0)
+    r1, e1 = learned.smooth_pair(apply_full, dinv, r, e)
+    assert np.linalg.norm(apply_full(e1) - r1) <= 1e-8 * np.linalg.norm(r1)
+    assert e1 @ r1 <= e @ r * (1 + 1e-12)
+    # the network's output scale does not matter
+    n = np.where(asm.active, rng.normal(size=r.size), 0.0)
+    za = learned.two_level(apply_full, dinv, r, lambda v: n)
+    zb = learned.two_level(apply_full, dinv, r, lambda v: -7.0 * n)
+    assert np.allclose(za, zb, rtol=1e-10, atol=1e-12 * np.abs(za).max())
+
+
+def test_fcg_with_exact_two_level_takes_one_iteration(small3d):
+    case, asm, dinv, apply_full, solve_full = small3d
+    bf = np.zeros(asm.grid.n_samples())
+    bf[asm.act_idx] = asm.b
+    pre = lambda r: learned.two_level(apply_full, dinv, r, solve_full)
+    x, it, hist, fb = learned.fcg(apply_full, bf, pre, dinv, tol=1e-9)
+    assert it == 1 and fb == 0
 
 
 # ------------------------------------------------------------------- Adam
