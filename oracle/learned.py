@@ -30,7 +30,9 @@ each piece below is written from its published definition:
 * Flexible CG with the Polak-Ribiere form of beta (Golub and Ye 1999;
   Notay 2000), so that a non-linear preconditioner can be used; a direction
   that is not a descent direction (z.r <= 0 or not finite) is replaced by
-  the Jacobi one.
+  the Jacobi one.  Its truncated form (Notay 2000) makes each new direction
+  A-orthogonal to the m previous ones instead of one, which keeps most of
+  CG's acceleration when the preconditioner varies from step to step.
 
 Everything is FP64.  ``bf16=True`` rounds to bfloat16 (round to nearest,
 ties to even) exactly where the GPU path stores bfloat16: the input tensor,
@@ -382,3 +384,41 @@ def fcg(apply_A, b, precond, dinv, tol=1e-6, max_iter=10000):
         k += 1
         hist.append(np.linalg.norm(r) / nb)
     return x, k, hist, fallbacks
+
+
+def fcg_truncated(apply_A, b, precond, dinv, m, tol=1e-6, max_iter=10000):
+    """Truncated flexible CG from x0 = 0: p_k = z_k - sum over the m previous
+    directions p_i of (z_k.A p_i / p_i.A p_i) p_i, alpha = p_k.r_k /
+    p_k.A p_k; z_k = M(r_k), replaced by the Jacobi z when z_k.r_k <= 0 or
+    not finite.  m = 1 is the Polak-Ribiere flexible CG of fcg().  Stops
+    when ||r|| <= tol ||b||.  Returns (x, iterations, history, fallbacks)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0, [0.0], 0
+    hist = [1.0]
+    P, Q = [], []
+    k = fallbacks = 0
+    while k < max_iter and hist[-1] > tol:
+        z = precond(r)
+        zr = float(z @ r)
+        if not np.isfinite(zr) or zr <= 0.0 or not np.all(np.isfinite(z)):
+            z = dinv * r
+            fallbacks += 1
+        p = z.copy()
+        for pi, qi in zip(P, Q):
+            p = p - (float(z @ qi) / float(pi @ qi)) * pi
+        q = apply_A(p)
+        alpha = float(p @ r) / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        P.append(p)
+        Q.append(q)
+        if len(P) > m:
+            P.pop(0)
+            Q.pop(0)
+        k += 1
+        hist.append(np.linalg.norm(r) / nb)
+    return x, k, hist, fallbacks
+

@@ -48,6 +48,9 @@ struct Loader {
     T beta;
     bool first;
     bool fb;   // MODE_FDIR: use the Jacobi z instead of zs
+    int mk;    // MODE_FDIR: previous directions subtracted
+    T bet[kFcgMax];
+    const T* prev[kFcgMax];
 
     // value of slice s at offset os (direction update in MODE_DIR / MODE_FDIR)
     __device__ __forceinline__ T value(long long os, bool own) const {
@@ -56,9 +59,16 @@ struct Loader {
             if (own && pout) pout[os] = z;
             return z;
         }
-        if (MODE == MODE_DIR || MODE == MODE_FDIR) {
-            const T z = (MODE == MODE_FDIR) ? (fb ? dinv[os] * r[os] : zs[os])
-                                            : (ZIN ? zs[os] : dinv[os] * r[os]);
+        if (MODE == MODE_FDIR) {
+            T val = fb ? dinv[os] * r[os] : zs[os];
+#pragma unroll
+            for (int i = 0; i < kFcgMax; ++i)
+                if (i < mk) val -= bet[i] * prev[i][os];
+            if (own) pout[os] = val;
+            return val;
+        }
+        if (MODE == MODE_DIR) {
+            const T z = ZIN ? zs[os] : dinv[os] * r[os];
             const T val = first ? z : z + beta * pin[os];
             if (own) pout[os] = val;
             return val;
@@ -77,6 +87,7 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
                                                 const T* __restrict__ bv, RedArgs ra) {
     T beta = T(0);
     bool first = true, fb = false;
+    T bet[kFcgMax] = {};
     if (MODE == MODE_DIR) {
         if (ra.sc->done) return;
         double bd;
@@ -87,10 +98,10 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
         if (ra.skip && *ra.skip) return;
     } else if (MODE == MODE_FDIR) {
         if (ra.sc->done) return;
-        double bd;
+        double bd[kFcgMax];
         if (!fcg_direction_preamble<NT>(ra, blockIdx.x, bd, fb)) return;
-        first = ra.kidx == 0;
-        beta = (T)bd;
+#pragma unroll
+        for (int i = 0; i < kFcgMax; ++i) bet[i] = (T)bd[i];
     }
     __shared__ T sW[2][6][HY][HX];
     __shared__ T gU[2][FY][FX];
@@ -99,7 +110,12 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
     const long long NP = g.NP;
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
-    Loader<T, MODE, ZIN> ld{g, r, zs, dinv, pin, pout, a, beta, first, fb};
+    Loader<T, MODE, ZIN> ld{g, r, zs, dinv, pin, pout, a, beta, first, fb, ra.fh.mk, {}, {}};
+#pragma unroll
+    for (int i = 0; i < kFcgMax; ++i) {
+        ld.bet[i] = bet[i];
+        ld.prev[i] = static_cast<const T*>(ra.fh.P[i]);
+    }
     double acc = 0.0;
   for (int wtile = blockIdx.x; wtile < tl.count; wtile += gridDim.x) {
     int i0, j0, k0;
@@ -291,6 +307,7 @@ __global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->pq = pq;
         sc->alpha = alpha_d;
+        sc->pqh[ra.kidx & 7] = pq;
     }
     const T alpha = (T)alpha_d;
     const long long NP = g.NP;

@@ -672,16 +672,16 @@ __global__ __launch_bounds__(CT) void k_coarse_prep(long long n, const float* __
 }
 
 // w from (n.r1, ., .) and (n.An) partials; z = a1 d + w n; partials of
-// (z.r, z.q, r.D^-1 q) for flexible CG; coef[1] = w.
+// (z.r, then z.Q_i and r.D^-1 Q_i for the previous directions of truncated
+// flexible CG, zero past fh.mk); coef[1] = w.
 __global__ __launch_bounds__(CT) void k_coarse_finish(long long n, const float* __restrict__ d,
                                                       const float* __restrict__ nv,
                                                       const float* __restrict__ r,
-                                                      const float* __restrict__ q,
                                                       const float* __restrict__ dinv,
                                                       double* coef,
                                                       const double* __restrict__ part_nr, int nb_nr,
                                                       const double* __restrict__ part_nq, int nb_nq,
-                                                      float* __restrict__ z,
+                                                      FcgHist fh, float* __restrict__ z,
                                                       double* __restrict__ part, const int* skip) {
     if (skip && *skip) return;
     double t3[3], t1[1];
@@ -690,18 +690,27 @@ __global__ __launch_bounds__(CT) void k_coarse_finish(long long n, const float* 
     const double wd = safe_ratio(t3[0], t1[0]);
     const float w = (float)wd, a1 = (float)coef[0];
     if (blockIdx.x == 0 && threadIdx.x == 0) coef[1] = wd;
-    double zr = 0.0, zq = 0.0, rdq = 0.0;
+    constexpr int NV = 1 + 2 * kFcgMax;
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    const int mk = fh.mk;
     for (long long t = blockIdx.x * (long long)CT + threadIdx.x; t < n;
          t += (long long)gridDim.x * CT) {
         const float zi = a1 * d[t] + w * nv[t];
         z[t] = zi;
-        const double ri = r[t], qi = q[t];
-        zr += (double)zi * ri;
-        zq += (double)zi * qi;
-        rdq += ri * (double)dinv[t] * qi;
+        const double ri = r[t], rd = ri * (double)dinv[t];
+        acc[0] += (double)zi * ri;
+#pragma unroll
+        for (int i = 0; i < kFcgMax; ++i) {
+            if (i < mk) {
+                const double qi = static_cast<const float*>(fh.Q[i])[t];
+                acc[1 + 2 * i] += (double)zi * qi;
+                acc[2 + 2 * i] += rd * qi;
+            }
+        }
     }
-    double vv[3] = {zr, zq, rdq};
-    block_partial<3, CT>(vv, part, gridDim.x, blockIdx.x);
+    block_partial<NV, CT>(acc, part, gridDim.x, blockIdx.x);
 }
 
 }  // namespace
@@ -894,12 +903,12 @@ void launch_coarse_prep(const Geo& g, const float* r, const float* qd, const flo
 }
 
 void launch_coarse_finish(const Geo& g, const float* d, const float* nv, const float* r,
-                          const float* q, const float* dinv, double* coef, const double* part_nr,
-                          int nb_nr, const double* part_nq, int nb_nq, float* z, double* part,
-                          const int* skip, hipStream_t s) {
+                          const float* dinv, double* coef, const double* part_nr, int nb_nr,
+                          const double* part_nq, int nb_nq, const FcgHist& fh, float* z,
+                          double* part, const int* skip, hipStream_t s) {
     hipLaunchKernelGGL(k_coarse_finish, dim3(coarse_blocks(g)), dim3(CT), 0, s,
-                       (long long)g.nsamp() * g.NP, d, nv, r, q, dinv, coef, part_nr, nb_nr, part_nq,
-                       nb_nq, z, part, skip);
+                       (long long)g.nsamp() * g.NP, d, nv, r, dinv, coef, part_nr, nb_nr, part_nq,
+                       nb_nq, fh, z, part, skip);
 }
 
 }  // namespace vfs

@@ -178,11 +178,13 @@ int run_chunks(vfs_ctx* ctx, Vecs<T>& v, bool set_bb, Scalars* out) {
     }
 }
 
-// Flexible CG iterations with the learned two-level preconditioner (3D,
-// FP32): z = a1 D^-1 r + w network(r1) from the (r.D^-1 r, r.r) partials
-// of the previous kernel (net_precond), then the direction (MODE_FDIR: z or
-// the Jacobi z, Polak-Ribiere beta) + apply, then the update.  Every launch
-// after a stop sees sc->done and does nothing.
+// Truncated flexible CG (kFcgMax previous directions) with the learned
+// two-level preconditioner (3D, FP32): z = a1 D^-1 r + w network(r1) from the
+// (r.D^-1 r, r.r) partials of the previous kernel (net_precond), then the
+// direction p = z - sum beta_i P_i (MODE_FDIR; Jacobi z when z is not a
+// descent direction) + apply, then the update.  Directions and their images
+// live in rings of kFcgMax + 1 slots.  Every launch after a stop sees
+// sc->done and does nothing.
 int run_chunks_fcg(vfs_ctx* ctx, Vecs<float>& v, bool set_bb, Scalars* out) {
     const Geo& g = ctx->g;
     const Parts P = parts(ctx);
@@ -191,25 +193,35 @@ int run_chunks_fcg(vfs_ctx* ctx, Vecs<float>& v, bool set_bb, Scalars* out) {
     const int nbA = apply_blocks(g, ctx->tiles), nbU = update_blocks(g, ctx->tiles);
     const int nbV = vec_grid_blocks(g), nbZ = coarse_blocks(g);
     const int* skip = &ctx->sc->done;
+    constexpr int R = kFcgMax + 1;
+    auto pring = [&](int k) { return net_vec(ctx, 5 + (k % R)); };
+    auto qring = [&](int k) { return net_vec(ctx, 5 + R + (k % R)); };
     int chunk = 4;
     int kidx = 0;
     for (;;) {
         for (int k = 0; k < chunk; ++k, ++kidx) {
-            float* pin = (kidx & 1) ? v.p1 : v.p0;
-            float* pout = (kidx & 1) ? v.p0 : v.p1;
+            FcgHist fh{};
+            fh.mk = std::min(kidx, kFcgMax);
+            for (int i = 0; i < fh.mk; ++i) {
+                fh.P[i] = pring(kidx - 1 - i);
+                fh.Q[i] = qring(kidx - 1 - i);
+            }
+            float* pout = pring(kidx);
+            float* q = qring(kidx);
             const int nb2 = kidx == 0 ? nbV : nbU;
             const bool timed = ctx->prof && k == 0;
             if (timed) HIPCHK(hipEventRecord(ctx->pev[3], s));
-            int rc = net_precond(u, ctx, v.r, v.dinv, v.a, v.c, v.K, P.B, nb2, v.q, skip);
+            int rc = net_precond(u, ctx, v.r, v.dinv, v.a, v.c, v.K, P.B, nb2, fh, skip);
             if (rc) return fail(ctx, rc, u->err);
-            const RedArgs ra{ctx->sc, net_region(ctx, 4), nbZ, P.A, kidx,
-                             (set_bb && kidx == 0) ? 1 : 0, P.B, nb2};
+            RedArgs ra{ctx->sc, net_region(ctx, 4), nbZ, P.A, kidx, (set_bb && kidx == 0) ? 1 : 0,
+                       P.B, nb2};
+            ra.fh = fh;
             const RedArgs rb{ctx->sc, P.A, nbA, P.B, kidx, 0};
             if (timed) HIPCHK(hipEventRecord(ctx->pev[0], s));
-            launch_apply<float>(g, ctx->tiles, MODE_FDIR, false, v.r, ctx->z32, v.dinv, pin, pout,
-                                v.q, v.a, v.c, v.K, nullptr, ra, s);
+            launch_apply<float>(g, ctx->tiles, MODE_FDIR, false, v.r, ctx->z32, v.dinv, nullptr,
+                                pout, q, v.a, v.c, v.K, nullptr, ra, s);
             if (timed) HIPCHK(hipEventRecord(ctx->pev[1], s));
-            launch_update<float>(g, ctx->tiles, v.x, pout, v.r, v.q, v.dinv, nullptr, rb, s);
+            launch_update<float>(g, ctx->tiles, v.x, pout, v.r, q, v.dinv, nullptr, rb, s);
             if (timed) HIPCHK(hipEventRecord(ctx->pev[2], s));
         }
         HIPCHK(hipGetLastError());
@@ -428,6 +440,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
     HIPCHK(hipGetLastError());
     ctx->assembled = true;
     ctx->dt_assembled = dt;
+    ctx->netvec_dirty = true;   // the active tiles may have changed
     return VFS_OK;
 }
 

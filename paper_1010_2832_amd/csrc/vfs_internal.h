@@ -80,6 +80,16 @@ struct Scalars {
     long long n_active;
     int fallbacks;      // flexible CG: iterations that used the Jacobi direction
     int pad[3];
+    double pqh[8];      // p.Ap of iteration k in slot k & 7 (truncated flexible CG)
+};
+
+// Truncated flexible CG: the m previous directions P_i and their images
+// Q_i = A P_i (i = 1 most recent), mk of them valid.
+constexpr int kFcgMax = 4;
+struct FcgHist {
+    const void* P[kFcgMax];
+    const void* Q[kFcgMax];
+    int mk;
 };
 
 // Partial-sum plumbing of one reduction-carrying launch.
@@ -93,6 +103,7 @@ struct RedArgs {
     const double* part_in2;  // flexible CG: (r.D^-1 r, r.r) partials of the update
     int nb_in2;
     const int* skip;         // MODE_JDIR: the launch does nothing if *skip != 0
+    FcgHist fh;              // MODE_FDIR: previous directions
 };
 
 // Compacted list of active 3D tiles (64 x 4 anchors in x,y times 8 planes
@@ -190,6 +201,7 @@ struct vfs_ctx {
     float* netvec = nullptr;
     double* netpart = nullptr;
     double* netcoef = nullptr;
+    bool netvec_dirty = true;    // the work space must be zeroed (new assembly)
     vfs_stats stats{};
     hipEvent_t ev[6] = {};
     bool prof = false;

@@ -172,22 +172,27 @@ __device__ __forceinline__ bool cg_direction_preamble(const RedArgs& ra, int bid
     return stop == 0;
 }
 
-// Preamble of a flexible-CG direction (Golub-Ye / Notay flexible CG with the
-// Polak-Ribiere beta).  Inputs: partials (z.r, z.q_prev, r.D^-1 q_prev) of
-// the preconditioner output z and partials (r.D^-1 r, r.r) of the update.
-// When z is not a descent direction (z.r <= 0 or non-finite) the Jacobi
-// direction D^-1 r is used instead (fb = true).  With r_k = r_{k-1} -
-// alpha q_{k-1}, beta = z_k.(r_k - r_{k-1}) / (z_{k-1}.r_{k-1})
-//                     = -alpha_{k-1} (z_k.q_{k-1}) / (z_{k-1}.r_{k-1}).
+// Preamble of a truncated flexible-CG direction (Notay 2000): the new
+// direction is p = z - sum_i beta_i P_i over the mk previous directions with
+// beta_i = z.Q_i / P_i.Q_i (Q_i = A P_i), which makes it A-orthogonal to
+// them; with mk = 1 this is the Polak-Ribiere flexible CG (Golub and Ye).
+// Inputs: partials (z.r, then z.Q_i and r.D^-1 Q_i for i = 1..kFcgMax) of the
+// preconditioner output z and partials (r.D^-1 r, r.r) of the update.  When
+// z is not a descent direction (z.r <= 0 or non-finite) the Jacobi direction
+// D^-1 r is used instead (fb = true).  beta[i] receives beta_{i+1}.
 template <int NT>
-__device__ __forceinline__ bool fcg_direction_preamble(const RedArgs& ra, int bid, double& beta,
-                                                       bool& fb) {
+__device__ __forceinline__ bool fcg_direction_preamble(const RedArgs& ra, int bid,
+                                                       double (&beta)[kFcgMax], bool& fb) {
     Scalars* sc = ra.sc;
-    double t3[3], t2[2];
-    reduce_partials<3, NT>(ra.part_in, ra.nb_in, t3);
+    constexpr int NV = 1 + 2 * kFcgMax;
+    double tz[NV], t2[2];
+    reduce_partials<NV, NT>(ra.part_in, ra.nb_in, tz);
     reduce_partials<2, NT>(ra.part_in2, ra.nb_in2, t2);
-    const double zr = t3[0], zq = t3[1], rdq = t3[2], rdr = t2[0], rr = t2[1];
-    fb = !(zr > 0.0) || !isfinite(zr) || (ra.kidx > 0 && !isfinite(zq));
+    const double zr = tz[0], rdr = t2[0], rr = t2[1];
+    const int mk = ra.fh.mk;
+    bool bad = !(zr > 0.0) || !isfinite(zr);
+    for (int i = 0; i < mk; ++i) bad = bad || !isfinite(tz[1 + 2 * i]);
+    fb = bad;
     const double rz = fb ? rdr : zr;
     const double bb = ra.set_bb ? rr : sc->bb;
     int stop = 0;
@@ -197,11 +202,16 @@ __device__ __forceinline__ bool fcg_direction_preamble(const RedArgs& ra, int bi
         stop = 1;
     else if (ra.kidx >= sc->max_iter)
         stop = 2;
-    beta = ra.kidx == 0 ? 0.0 : -sc->alpha * (fb ? rdq : zq) / sc->rz[(ra.kidx + 1) & 1];
+#pragma unroll
+    for (int i = 0; i < kFcgMax; ++i) {
+        const double pq = i < mk ? sc->pqh[(ra.kidx - 1 - i) & 7] : 0.0;
+        const double zq = fb ? tz[2 + 2 * i] : tz[1 + 2 * i];
+        beta[i] = (i < mk && pq > 0.0) ? zq / pq : 0.0;
+    }
     if (bid == 0 && threadIdx.x == 0) {
         sc->rz[ra.kidx & 1] = rz;
         sc->rr = rr;
-        sc->beta = beta;
+        sc->beta = beta[0];
         if (ra.set_bb) sc->bb = bb;
         if (fb && !stop) sc->fallbacks += 1;
         if (stop) {

@@ -138,9 +138,9 @@ void launch_coarse_prep(const Geo& g, const float* r, const float* qd, const flo
                         float* r1, double* part, double* coef, const float* d, double* r64,
                         double* e64, const int* skip, hipStream_t s);
 void launch_coarse_finish(const Geo& g, const float* d, const float* nv, const float* r,
-                          const float* q, const float* dinv, double* coef, const double* part_nr,
-                          int nb_nr, const double* part_nq, int nb_nq, float* z, double* part,
-                          const int* skip, hipStream_t s);
+                          const float* dinv, double* coef, const double* part_nr, int nb_nr,
+                          const double* part_nq, int nb_nq, const FcgHist& fh, float* z,
+                          double* part, const int* skip, hipStream_t s);
 
 }  // namespace vfs
 
@@ -187,19 +187,27 @@ struct vfs_unet {
 namespace vfs {
 constexpr int kMaxNetPartials = 1024;
 // partial regions of a context's preconditioner work space, each room for
-// 3 values x kNetPartCap workgroups
+// kNetPartVals values x kNetPartCap workgroups
 constexpr int kNetPartRegions = 5;
+constexpr int kNetPartVals = 1 + 2 * kFcgMax;
 constexpr int kNetPartCap = 1536;
+// work-space vectors: d, A d, r1, n, A n, then the direction and image rings
+// of truncated flexible CG (kFcgMax + 1 slots each)
+constexpr int kNetVecs = 5 + 2 * (kFcgMax + 1);
 // allocate the context's preconditioner work space (once)
 int net_bufs(vfs_ctx* ctx);
 // z (ctx->z32) = two-level preconditioner of the FP32 residual r; part_rdr:
-// (r.D^-1 r, .) partials of r; q_prev: the q whose (z.r, z.q, r.D^-1 q)
-// partials go to region 4 for flexible CG; skip: optional device flag.
+// (r.D^-1 r, .) partials of r; fh: previous directions whose (z.Q_i,
+// r.D^-1 Q_i) partials go with z.r to region 4 for flexible CG; skip:
+// optional device flag.
 int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, const float* a,
                 const float* c, const float* K, const double* part_rdr, int nb_rdr,
-                const float* q_prev, const int* skip);
+                const FcgHist& fh, const int* skip);
 inline double* net_region(vfs_ctx* ctx, int k) {
-    return ctx->netpart + (long long)k * 3 * kNetPartCap;
+    return ctx->netpart + (long long)k * kNetPartVals * kNetPartCap;
+}
+inline float* net_vec(vfs_ctx* ctx, int k) {
+    return ctx->netvec + (long long)k * ctx->g.nsamp() * ctx->g.NP;
 }
 // level-0 extents of the network tensor of a 3D grid
 Level net_level0(const Geo& g);

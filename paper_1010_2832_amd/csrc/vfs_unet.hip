@@ -235,8 +235,8 @@ int net_forward(vfs_unet* u, hipStream_t s, const int* skip) {
 int net_bufs(vfs_ctx* ctx) {
     if (ctx->netvec) return VFS_OK;
     const size_t n = (size_t)ctx->g.nsamp() * ctx->g.NP;
-    const size_t np = (size_t)kNetPartRegions * 3 * kNetPartCap;
-    if (hipMalloc(&ctx->netvec, 5 * n * sizeof(float)) != hipSuccess ||
+    const size_t np = (size_t)kNetPartRegions * kNetPartVals * kNetPartCap;
+    if (hipMalloc(&ctx->netvec, kNetVecs * n * sizeof(float)) != hipSuccess ||
         hipMalloc(&ctx->netpart, np * sizeof(double)) != hipSuccess ||
         hipMalloc(&ctx->netcoef, 4 * sizeof(double)) != hipSuccess) {
         if (ctx->netvec) (void)hipFree(ctx->netvec);
@@ -248,7 +248,7 @@ int net_bufs(vfs_ctx* ctx) {
         return ctx_fail(ctx, VFS_ENOMEM, "device allocation failed: preconditioner work space");
     }
     // entries outside the active tiles are read as halo values and stay zero
-    if (hipMemset(ctx->netvec, 0, 5 * n * sizeof(float)) != hipSuccess ||
+    if (hipMemset(ctx->netvec, 0, kNetVecs * n * sizeof(float)) != hipSuccess ||
         hipMemset(ctx->netcoef, 0, 4 * sizeof(double)) != hipSuccess)
         return ctx_fail(ctx, VFS_EHIP, "hipMemset failed");
     return VFS_OK;
@@ -256,7 +256,7 @@ int net_bufs(vfs_ctx* ctx) {
 
 int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, const float* a,
                 const float* c, const float* K, const double* part_rdr, int nb_rdr,
-                const float* q_prev, const int* skip) {
+                const FcgHist& fh, const int* skip) {
     const Geo& g = ctx->g;
     hipStream_t s = ctx->stream;
     const long long n = (long long)g.nsamp() * g.NP;
@@ -282,9 +282,8 @@ int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, co
     const RedArgs j2{ctx->sc, nullptr, 0, net_region(ctx, 3), 0, 0, nullptr, 0, skip};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, true, nullptr, NV, dinv, nullptr, nullptr, QN, a,
                         c, K, nullptr, j2, s);
-    launch_coarse_finish(g, D, NV, r, q_prev, dinv, ctx->netcoef, net_region(ctx, 2),
-                         net_unpack_blocks(g), net_region(ctx, 3), nbA, ctx->z32,
-                         net_region(ctx, 4), skip, s);
+    launch_coarse_finish(g, D, NV, r, dinv, ctx->netcoef, net_region(ctx, 2), net_unpack_blocks(g),
+                         net_region(ctx, 3), nbA, fh, ctx->z32, net_region(ctx, 4), skip, s);
     if (hipGetLastError() != hipSuccess) return ufail(u, VFS_EHIP, "launch failed");
     return VFS_OK;
 }
@@ -293,6 +292,13 @@ int net_prepare_ctx(vfs_unet* u, vfs_ctx* ctx) {
     const Geo& g = ctx->g;
     int rc = net_bufs(ctx);
     if (rc) return ufail(u, rc, ctx->err);
+    if (ctx->netvec_dirty) {
+        // the work vectors are read as halo values next to the active tiles:
+        // values a previous assembly left in now-inactive tiles must go
+        UCHK(hipMemsetAsync(ctx->netvec, 0,
+                            (size_t)kNetVecs * g.nsamp() * g.NP * sizeof(float), ctx->stream));
+        ctx->netvec_dirty = false;
+    }
     rc = net_ensure(u, net_level0(g), false);
     if (rc) return rc;
     launch_net_geometry(g, u->L[0], ctx->WL, ctx->WF, ctx->rho, ctx->mu, ctx->dt_assembled, u->x,
@@ -592,8 +598,9 @@ int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z) {
     launch_mask(ctx->r, ctx->z, ctx->a, n, s);
     launch_to_f32(ctx->r, ctx->r32, n, s);
     launch_net_rdr(g, ctx->r32, ctx->dinv32, u->dpart, s);
+    FcgHist none{};
     rc = net_precond(u, ctx, ctx->r32, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32, u->dpart,
-                     net_rdr_blocks(g), ctx->r32, nullptr);
+                     net_rdr_blocks(g), none, nullptr);
     if (rc) return ctx_fail(ctx, rc, u->err);
     launch_f32_to_f64(ctx->z32, ctx->z, n, s);
     if (hipGetLastError() != hipSuccess) return ctx_fail(ctx, VFS_EHIP, "launch failed");

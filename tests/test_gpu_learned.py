@@ -237,6 +237,29 @@ def test_fcg_with_untrained_network_converges_to_oracle(V, L):
     net.close()
 
 
+def test_fcg_with_zero_network_is_jacobi_pcg(V, L):
+    """A zero network makes the two-level step a multiple of the Jacobi
+    direction, a fixed SPD preconditioner: truncated flexible CG then
+    reduces to Jacobi PCG and needs the same number of iterations."""
+    case = cases.pool3d(24, seed=25)
+    ctx = V.context_from_case(case, precision=V.VFS_MIXED, tol=1e-6)
+    zero = V.Unet()
+    zero.vfs_unet_set_weights(np.zeros(V.vfs_unet_param_count(), np.float32))
+    ctx.vfs_set_preconditioner(zero)
+    its = {}
+    for name, pc in (("jacobi", V.VFS_PRECOND_JACOBI), ("learned", V.VFS_PRECOND_LEARNED)):
+        ctx.vfs_set_solver(pc, V.VFS_MIXED, 1e-6, 20000)
+        ctx.vfs_set_velocity(case["u"])
+        ctx.vfs_step(case["dt"])
+        st = ctx.vfs_get_stats()
+        its[name] = st["iterations"]
+        assert st["rel_residual"] <= 1e-6
+    _banner(f"zero network: FCG {its['learned']} it, Jacobi PCG {its['jacobi']} it")
+    assert abs(its["learned"] - its["jacobi"]) <= 2 + 0.03 * its["jacobi"]
+    ctx.close()
+    zero.close()
+
+
 def _step_gain(ctx, r, e):
     """A-norm error left by one preconditioner application with exact line
     search, relative to the error before: 1 - (z.r)^2 / ((z.A z)(e.r))."""

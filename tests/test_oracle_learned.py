@@ -297,3 +297,29 @@ def test_fcg_replaces_non_descent_directions_by_jacobi(small3d):
     x2, it2, _, fb2 = learned.fcg(apply_full, bf, lambda r: dinv * r, dinv, tol=1e-8)
     assert fb1 == it1 and fb2 == 0 and it1 == it2
     assert np.allclose(x1, x2)
+
+
+def test_truncated_fcg_reductions(small3d):
+    """m = 1 is the Polak-Ribiere flexible CG; with a fixed SPD preconditioner
+    the extra orthogonalisations vanish and every m gives PCG; with the exact
+    inverse one iteration suffices."""
+    case, asm, dinv, apply_full, solve_full = small3d
+    bf = np.zeros(asm.grid.n_samples())
+    bf[asm.act_idx] = asm.b
+    rng = np.random.default_rng(16)
+    n = np.where(asm.active, rng.normal(size=bf.size), 0.0)
+    # a non-linear preconditioner: the two-level step with a fixed "network"
+    pre = lambda r: learned.two_level(apply_full, dinv, r, lambda v: n * np.sign(v @ n + 1e-300))
+    x1, k1, h1, _ = learned.fcg(apply_full, bf, pre, dinv, tol=1e-8, max_iter=200)
+    x2, k2, h2, _ = learned.fcg_truncated(apply_full, bf, pre, dinv, 1, tol=1e-8, max_iter=200)
+    kk = min(30, k1, k2)
+    assert np.allclose(h1[:kk], h2[:kk], rtol=1e-6)
+    jac = lambda r: dinv * r
+    _, kj, hj = cg.jacobi_pcg(asm.A.tocsr(), asm.b, tol=1e-8)
+    for m in (1, 3, 8):
+        _, km, hm, fb = learned.fcg_truncated(apply_full, bf, jac, dinv, m, tol=1e-8)
+        assert fb == 0 and abs(km - kj) <= 1 + 0.02 * kj   # rounding drift near convergence
+        assert np.allclose(hm[:20], hj[:20], rtol=1e-6)
+    _, k3, _, _ = learned.fcg_truncated(apply_full, bf, solve_full, dinv, 4, tol=1e-9)
+    assert k3 == 1
+
