@@ -1,0 +1,56 @@
+"""Compare Jacobi PCG with flexible CG and the learned preconditioner.
+
+    python -m paper_1010_2832_amd.eval_precond --weights W.npy 64:143:6000 256:5:3000
+
+Each argument is n:seed:max_iter for a seeded 3D pool problem (seed 5 with
+n = 256 is the 256^3 benchmark configuration).  Both solvers run the full
+step in VFS_MIXED arithmetic to a 1e-6 FP64 relative residual, capped at
+max_iter iterations; the line per solver gives iterations, device solve
+time, the final residual and the live per-iteration kernel times.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--weights", required=True)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("cases", nargs="+")
+    a = ap.parse_args(argv)
+
+    import cases
+    from paper_1010_2832_amd import vfstokes as V
+
+    net = V.Unet()
+    net.vfs_unet_set_weights(np.load(a.weights, allow_pickle=False).astype(np.float32))
+    for spec in a.cases:
+        n, seed, cap = (int(q) for q in spec.split(":"))
+        c = cases.config5(n=n) if seed == 5 else cases.pool3d(n, seed=seed)
+        ctx = V.context_from_case(c, precision=V.VFS_MIXED, tol=a.tol)
+        ctx.vfs_set_preconditioner(net)
+        for name, pc in (("jacobi", V.VFS_PRECOND_JACOBI), ("learned", V.VFS_PRECOND_LEARNED)):
+            ctx.vfs_set_solver(pc, V.VFS_MIXED, a.tol, cap)
+            ctx.vfs_set_velocity(c["u"])
+            ctx.vfs_set_profiling(True)
+            ctx.vfs_step(c["dt"], allow_unconverged=True)
+            st = ctx.vfs_get_stats()
+            print(f"n={n} seed={seed} {name}: {st['iterations']} it, solve {st['t_solve_ms']:.1f} ms, "
+                  f"rel {st['rel_residual']:.2e}, active {st['n_active']}, apply "
+                  f"{st['t_apply_avg_ms']:.3f} ms, update {st['t_update_avg_ms']:.3f} ms, precond "
+                  f"{st['t_precond_avg_ms']:.3f} ms, fallbacks {st['precond_fallbacks']}", flush=True)
+        ctx.close()
+    net.close()
+
+
+if __name__ == "__main__":
+    main()
