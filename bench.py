@@ -12,9 +12,10 @@ hot path: body force, fractions, coefficients, null-space elimination,
 right-hand side, PCG solve, velocity recovery.
 
 value = sum over timed steps of (active DOFs x CG iterations) / timed wall
-time, in DOF*iter/s.  The roofline object reports the dominant kernel (the
-fused direction/apply kernel) against MI355X HBM peak, with its average
-launch duration measured live by HIP events on the context stream.
+time, in DOF*iter/s.  The roofline object reports the dominant kernel (in
+the 2D mixed inner solve the fused PCG iteration, one launch per iteration)
+against MI355X HBM peak, with its average launch duration measured live by
+HIP events on the context stream.
 """
 from __future__ import annotations
 
@@ -44,12 +45,20 @@ def algorithmic_bytes(dim, precision, n_active):
     return (5.0 + c) * word * n_active, 7.0 * word * n_active
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_apply2d_pool512_mixed_counters.md")
-KERNEL_SOURCES = ("paper_1010_2832_amd/csrc/k_pcg.hip", "paper_1010_2832_amd/csrc/vfs_reduce.h")
+def fused_bytes(precision, n_active):
+    """Bytes one fused 2D CG iteration (one launch) must move: read r, q, p,
+    D^-1, x and the c = 2 coefficients per DOF, write r, x, p, q -> 11 values
+    per active DOF."""
+    word = 4 if precision == 1 else 8
+    return 11.0 * word * n_active
+
+
+COUNTERS = os.path.join(ROOT, "profiles", "k_fused2d_pool512_mixed_counters.md")
+KERNEL_SOURCES = ("paper_1010_2832_amd/csrc/k_fused2d.hip", "paper_1010_2832_amd/csrc/vfs_reduce.h")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the 2D apply kernel from the committed
+    """HBM bytes per launch of the fused 2D CG kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources
     changed since the counters were taken (or the summary is absent)."""
     import hashlib
@@ -60,7 +69,7 @@ def measured_traffic():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    m = re.search(r"sha256 \(k_pcg.hip \+ vfs_reduce.h\): ([0-9a-f]+)", text)
+    m = re.search(r"sha256 \(k_fused2d.hip \+ vfs_reduce.h\): ([0-9a-f]+)", text)
     t = re.search(r"HBM traffic per launch \(bytes, scaled\) \| ([0-9.eE+-]+)", text)
     if not m or not t or m.group(1) != h.hexdigest():
         return None
@@ -150,12 +159,18 @@ def main():
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
 
-    b_apply, b_update = algorithmic_bytes(2, prec, n_act)
     ta, tu = st["t_apply_avg_ms"], st["t_update_avg_ms"]
-    if ta * b_update / max(b_apply, 1) >= tu:
-        dom, bytes_, t_ms = "k_apply2d (fused direction update + matrix-free apply + p.Ap)", b_apply, ta
+    if prec == V.VFS_MIXED:
+        # one fused launch per CG iteration in the 2D mixed inner solve
+        dom = ("k_fused2d (one launch per PCG iteration: lazy x, r update, Jacobi, direction, "
+               "matrix-free A p, five FP64 partials)")
+        bytes_, t_ms = fused_bytes(prec, n_act), ta
     else:
-        dom, bytes_, t_ms = "k_update (x, r update + Jacobi + r.z, r.r)", b_update, tu
+        b_apply, b_update = algorithmic_bytes(2, prec, n_act)
+        if ta * b_update / max(b_apply, 1) >= tu:
+            dom, bytes_, t_ms = "k_apply2d (fused direction update + matrix-free apply + p.Ap)", b_apply, ta
+        else:
+            dom, bytes_, t_ms = "k_update (x, r update + Jacobi + r.z, r.r)", b_update, tu
     achieved = bytes_ / (t_ms * 1e-3) / 1e9 if t_ms > 0 else 0.0
 
     out = {
@@ -181,8 +196,8 @@ def main():
                    "assemble_ms": st["t_assemble_ms"], "recover_ms": st["t_recover_ms"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if (args.n == 512 and dom.startswith("k_apply2d")
-                                                       and prec == V.VFS_MIXED) else None,
+                     "traffic": measured_traffic() if (args.n == 512 and dom.startswith("k_fused2d"))
+                                else None,
                      "avg_launch_ms": t_ms, "launches_timed": int(st["n_apply_timed"]),
                      "algorithmic_bytes_per_launch": bytes_,
                      "apply_avg_ms": ta, "update_avg_ms": tu},

@@ -26,6 +26,25 @@ constexpr int TX = 64, TY = 4, KZ = 8, NT = 256;
 constexpr int HX = TX + 2, HY = TY + 2;
 constexpr int FX = TX + 1, FY = TY + 1;
 
+// XCD-aware assignment of the active-tile list to workgroups.  Workgroups
+// are dispatched round-robin over the 8 XCDs of the chip, so workgroup b runs
+// on XCD b % 8.  Each XCD takes one contiguous eighth of the list (tiles in
+// x order, then y, then z), so tiles that share halo cache lines, and the
+// apply and the update of the same tile, stay within one XCD's L2.  With
+// fewer than 8 workgroups the list is simply strided.
+struct TileRange {
+    int first, step, end;
+};
+
+__device__ __forceinline__ TileRange tile_range(int count) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G < 8) return TileRange{b, G, count};
+    const int x = b & 7, slot = b >> 3;
+    const int nblk = (G - x + 7) >> 3;   // workgroups on this XCD
+    const int t0 = (int)((long long)count * x / 8), t1 = (int)((long long)count * (x + 1) / 8);
+    return TileRange{t0 + slot, nblk, t1};
+}
+
 __device__ __forceinline__ void tile_origin(const Tiles& t, int w, int& i0, int& j0, int& k0) {
     const int id = t.list[w];
     const int tx = id % t.ntx;
@@ -117,7 +136,8 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
         ld.prev[i] = static_cast<const T*>(ra.fh.P[i]);
     }
     double acc = 0.0;
-  for (int wtile = blockIdx.x; wtile < tl.count; wtile += gridDim.x) {
+  const TileRange tr = tile_range(tl.count);
+  for (int wtile = tr.first; wtile < tr.end; wtile += tr.step) {
     int i0, j0, k0;
     tile_origin(tl, wtile, i0, j0, k0);
     const int kend = min(k0 + KZ, g.nz + 1);
@@ -312,7 +332,8 @@ __global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict_
     const T alpha = (T)alpha_d;
     const long long NP = g.NP;
     double rz = 0.0, rr = 0.0;
-    for (int wtile = blockIdx.x; wtile < tl.count; wtile += gridDim.x) {
+    const TileRange tr = tile_range(tl.count);
+  for (int wtile = tr.first; wtile < tr.end; wtile += tr.step) {
         int i0, j0, k0;
         tile_origin(tl, wtile, i0, j0, k0);
         const int kend = min(k0 + KZ, g.nz + 1);
@@ -397,12 +418,36 @@ void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* cou
     hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, n, flags, list, count);
 }
 
+// Workgroups of a 3D apply launch: no more than can be resident at once
+// (occupancy x compute units, queried once per device and precision), so no
+// tail wave runs after the first, and at most kMaxTileBlocks.
+int apply3d_grid(int count, int word) {
+    static int cache[2][16] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int& c = cache[word == 8 ? 1 : 0][dev & 15];
+    if (c == 0) {
+        int nb = 0, ncu = 0;
+        const hipError_t e =
+            word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, k_apply3d<double, MODE_DIR, false>, NT, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                            &nb, k_apply3d<float, MODE_DIR, false>, NT, 0);
+        if (e != hipSuccess || nb < 1) nb = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu < 1)
+            ncu = 1;
+        c = nb * ncu;
+    }
+    return std::max(1, std::min(std::min(count, kMaxTileBlocks), c));
+}
+
 template <typename T>
 void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,
                     const T* dinv, const T* pin, T* pout, T* q, const T* a, const T* c,
                     const T* K, const T* bvec, const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    const dim3 gs(std::min(tl.count, kMaxTileBlocks));
+    const dim3 gs(apply3d_grid(tl.count, (int)sizeof(T)));
     if (mode == MODE_DIR) {
         if (zin)
             hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,

@@ -1,0 +1,322 @@
+// 2D Jacobi-preconditioned CG with one fused kernel per iteration.
+//
+// Plain PCG (the update x += alpha p, r -= alpha q, then z = D^-1 r, then
+// p = z + beta p, q = A p) needs two global reductions per iteration: p.q
+// before the update and r.z before the next direction.  Here the update of
+// iteration k-1 is carried out lazily by launch k, and r_k.z_k is obtained
+// one launch early from quantities reduced together with p.q:
+//   r_k.z_k = r_{k-1}.z_{k-1} - 2 alpha q_{k-1}.D^-1 r_{k-1}
+//             + alpha^2 q_{k-1}.D^-1 q_{k-1},
+// re-anchored every step on the directly summed r_{k-1}.z_{k-1}, so the
+// expansion error does not accumulate.  q = A p is always applied
+// explicitly (no recurrence for A p), so the iterates are those of plain PCG
+// up to the rounding of beta.  The matrix is the paper's
+// A = dt B^T K B + Dg (eq. stokesmixedsystemspd, factored form of Section 8),
+// applied with the same LDS-tiled stencil as k_apply2d.
+//
+// Launch k >= 1, from the partials (r.z, p.q, q.D^-1 r, q.D^-1 q, r.r) of
+// launch k-1:
+//   stop test on r_{k-1}.r_{k-1};  alpha = r.z / p.q;  beta from the
+//   expansion;  on the tile and its halo: r_k = r_{k-1} - alpha q_{k-1},
+//   z_k = D^-1 r_k, p_k = z_k + beta p_{k-1}; at the own anchors also
+//   x_k = x_{k-1} + alpha p_{k-1}; then q_k = A p_k and the partials of
+//   iteration k.
+// Launch 0 (init) forms z_0 = D^-1 r_0, p_0 = z_0, q_0 = A p_0 and the first
+// partials.  r, p and q are double-buffered by launch parity because the
+// halo of launch k reads the values of launch k-1 that neighbouring
+// workgroups overwrite; x is read and written only at the own anchors.
+#include "vfs_internal.h"
+#include "vfs_reduce.h"
+
+#include <algorithm>
+
+namespace vfs {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NV = 5;   // r.z, p.q, q.D^-1 r, q.D^-1 q, r.r
+
+// Launched over the compacted list of tiles that hold an active sample;
+// the vectors of the other tiles stay zero (they hold no active sample), so
+// their values read as halo are correct.
+template <typename T, bool INIT, int BX, int BY>
+__global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __restrict__ dinv,
+                                                const T* __restrict__ a, const T* __restrict__ c,
+                                                const T* __restrict__ K, const int* __restrict__ tiles,
+                                                int ntx, RedArgs ra) {
+    constexpr int RPT = BY * BX / NT;
+    constexpr int NE1 = ((BX + 2) * (BY + 2) + NT - 1) / NT;
+    constexpr int NE2 = ((BX + 1) * (BY + 1) + NT - 1) / NT;
+    const int bid = blockIdx.x;
+    Scalars* sc = ra.sc;
+    if (!INIT && sc->done) return;
+    const int k = ra.kidx;
+    const int pin = (k + 1) & 1, pout = k & 1;   // launch k reads slot (k-1)&1, writes k&1
+    const T* __restrict__ r_in = static_cast<const T*>(v.r[INIT ? 0 : pin]);
+    const T* __restrict__ q_in = static_cast<const T*>(v.q[pin]);
+    const T* __restrict__ p_in = static_cast<const T*>(v.p[pin]);
+    T* __restrict__ r_out = static_cast<T*>(v.r[pout]);
+    T* __restrict__ p_out = static_cast<T*>(v.p[pout]);
+    T* __restrict__ q_out = static_cast<T*>(v.q[pout]);
+    T* __restrict__ x = static_cast<T*>(v.x);
+    __shared__ T sV[3][BY + 2][BX + 2];   // p_k
+    __shared__ T sW[3][BY + 2][BX + 2];   // a p_k
+    __shared__ T sZ[3][BY + 2][BX + 2];   // z_k
+    __shared__ T sD[3][BY + 2][BX + 2];   // D^-1
+    __shared__ T sG[2][BY + 1][BX + 1];
+    const long long NP = g.NP;
+    const int tile = tiles[bid];
+    const int i0 = (tile % ntx) * BX, j0 = (tile / ntx) * BY;
+    const int tid = threadIdx.x;
+
+    // (1) partials of the previous launch
+    PartialLoads<NV, NT, 4> pl;
+    if (!INIT) pl.load(ra.part_in, ra.nb_in);
+
+    // (2) loads that do not depend on the totals
+    T Rr[NE1][3], Dd[NE1][3], Qq[NE1][3], Pp[NE1][3], Aa[NE1][3], Xx[NE1][3];
+    bool in1[NE1], own1[NE1];
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+        const int e = tid + m * NT;
+        const int li = e % (BX + 2), lj = e / (BX + 2);
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        in1[m] = e < (BX + 2) * (BY + 2) && i <= g.nx + 1 && j <= g.ny + 1;
+        own1[m] = in1[m] && li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
+        const long long o = in1[m] ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const long long os = o + s * NP;
+            Rr[m][s] = Dd[m][s] = Qq[m][s] = Pp[m][s] = Aa[m][s] = Xx[m][s] = T(0);
+            if (in1[m]) {
+                Rr[m][s] = r_in[os];
+                Dd[m][s] = dinv[os];
+                Aa[m][s] = a[os];
+                if (!INIT) {
+                    Qq[m][s] = q_in[os];
+                    Pp[m][s] = p_in[os];
+                }
+            }
+            if (!INIT && own1[m]) Xx[m][s] = x[os];
+        }
+    }
+    T Ku[NE2], Kv[NE2];
+#pragma unroll
+    for (int m = 0; m < NE2; ++m) {
+        const int e = tid + m * NT;
+        const int li = e % (BX + 1), lj = e / (BX + 1);
+        Ku[m] = Kv[m] = T(0);
+        if (e < (BX + 1) * (BY + 1)) {
+            const int iu = i0 + li, ju = j0 - 1 + lj;
+            if (iu <= g.nx && ju >= 0 && ju < g.ny) Ku[m] = K[g.idx(iu, ju)];
+            const int iv = i0 - 1 + li, jv = j0 + lj;
+            if (iv >= 0 && iv < g.nx && jv <= g.ny) Kv[m] = K[NP + g.idx(iv, jv)];
+        }
+    }
+    const int tx = tid % BX;
+    T Ao[RPT][3], Co[RPT][2];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = tid / BX + rr * (NT / BX);
+        const int i = i0 + tx, j = j0 + ty;
+        const bool ok = i <= g.nx && j <= g.ny;
+        const long long o = ok ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) Ao[rr][s] = ok ? a[o + s * NP] : T(0);
+        Co[rr][0] = ok ? c[NP + o] : T(0);
+        Co[rr][1] = ok ? c[2 * NP + o] : T(0);
+    }
+
+    // (3) totals of iteration k-1 -> stop decision, alpha_{k-1}, beta_k
+    T alpha = T(0), beta = T(0);
+    if (!INIT) {
+        double t[NV];
+        pl.finish(t);
+        const double rz = t[0], pq = t[1], qdr = t[2], qdq = t[3], rrk = t[4];
+        const double bb = ra.set_bb ? rrk : sc->bb;
+        int stop = 0;
+        if (!isfinite(rz) || !isfinite(rrk) || !isfinite(pq))
+            stop = 3;
+        else if (rrk <= sc->tol2 * bb)
+            stop = 1;
+        else if (k - 1 >= sc->max_iter)
+            stop = 2;
+        else if (!(pq > 0.0))
+            stop = 3;
+        const double ad = stop ? 0.0 : rz / pq;
+        const double rzn = rz - 2.0 * ad * qdr + ad * ad * qdq;
+        const double bd = (rz > 0.0) ? rzn / rz : 0.0;
+        if (bid == 0 && tid == 0) {
+            sc->rz[k & 1] = rz;
+            sc->rr = rrk;
+            sc->pq = pq;
+            sc->alpha = ad;
+            sc->beta = bd;
+            if (ra.set_bb) sc->bb = bb;
+            if (stop) {
+                sc->done = stop;
+                sc->iter = k - 1;
+            }
+        }
+        if (stop) return;
+        alpha = (T)ad;
+        beta = (T)bd;
+    }
+
+    // (4) tile and halo: r_k, z_k, p_k; own anchors also x_k
+    double rz_n = 0.0, rr_n = 0.0;
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+        const int e = tid + m * NT;
+        if (e >= (BX + 2) * (BY + 2)) continue;
+        const int li = e % (BX + 2), lj = e / (BX + 2);
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        const long long o = in1[m] ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const T rn = INIT ? Rr[m][s] : Rr[m][s] - alpha * Qq[m][s];
+            const T zn = Dd[m][s] * rn;
+            const T pn = INIT ? zn : zn + beta * Pp[m][s];
+            if (own1[m]) {
+                const long long os = o + s * NP;
+                if (!INIT) {
+                    r_out[os] = rn;
+                    x[os] = Xx[m][s] + alpha * Pp[m][s];
+                }
+                p_out[os] = pn;
+                rz_n += (double)rn * (double)zn;
+                rr_n += (double)rn * (double)rn;
+            }
+            sV[s][lj][li] = pn;
+            sW[s][lj][li] = Aa[m][s] * pn;
+            sZ[s][lj][li] = zn;
+            sD[s][lj][li] = Dd[m][s];
+        }
+    }
+    __syncthreads();
+
+    // (5) faces: g = K (B p)
+#pragma unroll
+    for (int m = 0; m < NE2; ++m) {
+        const int e = tid + m * NT;
+        if (e >= (BX + 1) * (BY + 1)) continue;
+        const int li = e % (BX + 1), lj = e / (BX + 1);
+        sG[0][lj][li] = Ku[m] * ((sW[0][lj][li + 1] - sW[0][lj][li]) +
+                                 (sW[1][lj][li] - sW[1][lj][li + 1]) +
+                                 (sW[2][lj][li + 1] - sW[2][lj + 1][li + 1]));
+        sG[1][lj][li] = Kv[m] * ((sW[0][lj + 1][li] - sW[0][lj][li]) +
+                                 (sW[1][lj + 1][li] - sW[1][lj][li]) +
+                                 (sW[2][lj + 1][li] - sW[2][lj + 1][li + 1]));
+    }
+    __syncthreads();
+
+    // (6) q_k = B^T g + Dg p at the anchors; partials of p.q, q.z, q.D^-1 q
+    double pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = tid / BX + rr * (NT / BX);
+        const int i = i0 + tx, j = j0 + ty;
+        if (i <= g.nx && j <= g.ny) {
+            const long long o = g.idx(i, j);
+            const T gu0 = sG[0][ty + 1][tx], gu1 = sG[0][ty + 1][tx + 1], gum = sG[0][ty][tx];
+            const T gv0 = sG[1][ty][tx + 1], gv1 = sG[1][ty + 1][tx + 1], gvm = sG[1][ty][tx];
+            T y[3];
+            y[0] = Ao[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
+            y[1] = Ao[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * sV[1][ty + 1][tx + 1];
+            y[2] = Ao[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * sV[2][ty + 1][tx + 1];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                q_out[o + s * NP] = y[s];
+                const double yd = y[s];
+                pq_n += (double)sV[s][ty + 1][tx + 1] * yd;
+                qz_n += (double)sZ[s][ty + 1][tx + 1] * yd;
+                qdq_n += (double)sD[s][ty + 1][tx + 1] * yd * yd;
+            }
+        }
+    }
+    double vv[NV] = {rz_n, pq_n, qz_n, qdq_n, rr_n};
+    block_partial<NV, NT>(vv, ra.part_out, gridDim.x, bid);
+}
+
+// tile t (BX x BY anchors) is active if any of its samples has a != 0
+template <int BX, int BY>
+__global__ __launch_bounds__(NT) void k_tiles2d_flags(Geo g, int ntx, const double* __restrict__ a,
+                                                      int* __restrict__ flags) {
+    const int t = blockIdx.x;
+    const int i0 = (t % ntx) * BX, j0 = (t / ntx) * BY;
+    int any = 0;
+    for (int e = threadIdx.x; e < BX * BY; e += NT) {
+        const int i = i0 + e % BX, j = j0 + e / BX;
+        if (i <= g.nx && j <= g.ny)
+            for (int s = 0; s < 3; ++s) any |= a[s * g.NP + g.idx(i, j)] != 0.0;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) flags[t] = any;
+}
+
+// ordered compaction of the active tile ids (one workgroup)
+__global__ __launch_bounds__(1024) void k_tiles2d_compact(int n, const int* __restrict__ flags,
+                                                          int* __restrict__ list,
+                                                          int* __restrict__ count) {
+    __shared__ int s_cnt[1024];
+    const int per = (n + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    int c = 0;
+    for (int t = lo; t < hi; ++t) c += flags[t];
+    s_cnt[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int q = 0; q < 1024; ++q) {
+            const int v = s_cnt[q];
+            s_cnt[q] = run;
+            run += v;
+        }
+        *count = run;
+    }
+    __syncthreads();
+    int w = s_cnt[threadIdx.x];
+    for (int t = lo; t < hi; ++t)
+        if (flags[t]) list[w++] = t;
+}
+
+// tile shape: 64 x 8 anchors was the fastest of 64x8, 128x4, 64x4 and 32x8 on
+// the 512^2 workload (463.7, 466.2, 481.1 and 510.0 ms per step)
+constexpr int kBX = 64, kBY = 8;
+
+}  // namespace
+
+void fused2d_tile_dims(const Geo& g, int& ntx, int& nty) {
+    ntx = (g.nx + 1 + kBX - 1) / kBX;
+    nty = (g.ny + 1 + kBY - 1) / kBY;
+}
+
+void launch_tiles2d(const Geo& g, const double* a, int* flags, int* list, int* count,
+                    hipStream_t s) {
+    int ntx, nty;
+    fused2d_tile_dims(g, ntx, nty);
+    const int n = ntx * nty;
+    hipLaunchKernelGGL((k_tiles2d_flags<kBX, kBY>), dim3(n), dim3(NT), 0, s, g, ntx, a, flags);
+    hipLaunchKernelGGL(k_tiles2d_compact, dim3(1), dim3(1024), 0, s, n, flags, list, count);
+}
+
+template <typename T>
+void launch_fused2d(const Geo& g, bool init, const FusedVecs& v, const T* dinv, const T* a,
+                    const T* c, const T* K, const int* tiles, int count, const RedArgs& ra,
+                    hipStream_t s) {
+    if (count <= 0) return;
+    int ntx, nty;
+    fused2d_tile_dims(g, ntx, nty);
+    if (init)
+        hipLaunchKernelGGL((k_fused2d<T, true, kBX, kBY>), dim3(count), dim3(NT), 0, s, g, v, dinv,
+                           a, c, K, tiles, ntx, ra);
+    else
+        hipLaunchKernelGGL((k_fused2d<T, false, kBX, kBY>), dim3(count), dim3(NT), 0, s, g, v, dinv,
+                           a, c, K, tiles, ntx, ra);
+}
+
+template void launch_fused2d<float>(const Geo&, bool, const FusedVecs&, const float*, const float*,
+                                    const float*, const float*, const int*, int, const RedArgs&,
+                                    hipStream_t);
+
+}  // namespace vfs

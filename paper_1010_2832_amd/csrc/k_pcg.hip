@@ -386,8 +386,8 @@ int vec_grid_blocks(const Geo& g) {
     return (int)nb;
 }
 
-int apply_blocks(const Geo& g, const Tiles& tl) {
-    return g.dim == 2 ? apply_grid_blocks(g) : std::min(tl.count, kMaxTileBlocks);
+int apply_blocks(const Geo& g, const Tiles& tl, int word) {
+    return g.dim == 2 ? apply_grid_blocks(g) : apply3d_grid(tl.count, word);
 }
 
 int update_blocks(const Geo& g, const Tiles& tl) {

@@ -142,7 +142,7 @@ template <typename T>
 int run_chunks(vfs_ctx* ctx, Vecs<T>& v, bool set_bb, Scalars* out) {
     const Geo& g = ctx->g;
     const Parts P = parts(ctx);
-    const int nbA = apply_blocks(g, ctx->tiles), nbU = update_blocks(g, ctx->tiles);
+    const int nbA = apply_blocks(g, ctx->tiles, (int)sizeof(T)), nbU = update_blocks(g, ctx->tiles);
     const int nbV = vec_grid_blocks(g);
     int chunk = 8;
     int kidx = 0;
@@ -178,6 +178,48 @@ int run_chunks(vfs_ctx* ctx, Vecs<T>& v, bool set_bb, Scalars* out) {
     }
 }
 
+// 2D PCG with one fused launch per iteration (k_fused2d.hip) in FP32 over the
+// tiles holding an active sample, on the residual that launch_cg_init placed
+// in r32 (x32 = 0): an init launch
+// (p = D^-1 r, q = A p, first partials), then launch k = 1, 2, ... carries
+// out iteration k-1's update and forms direction k; partials alternate
+// between two regions.
+int run_chunks_fused(vfs_ctx* ctx, bool set_bb, Scalars* out) {
+    const Geo& g = ctx->g;
+    hipStream_t s = ctx->stream;
+    const int nb = ctx->tiles2d;
+    double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)nb + 32};
+    const FusedVecs fv{ctx->x32, {ctx->r32, ctx->z32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
+    const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
+    launch_fused2d<float>(g, true, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32, ctx->tile_list,
+                          nb, r0, s);
+    int chunk = 8;
+    int kidx = 1;
+    for (;;) {
+        // live timing: the launches 2..chunk of a chunk back to back (the
+        // first follows a host synchronisation and starts cold)
+        for (int k = 0; k < chunk; ++k, ++kidx) {
+            const RedArgs ra{ctx->sc, part[(kidx + 1) & 1], nb, part[kidx & 1], kidx,
+                             (set_bb && kidx == 1) ? 1 : 0};
+            if (ctx->prof && k == 1) HIPCHK(hipEventRecord(ctx->pev[0], s));
+            launch_fused2d<float>(g, false, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32,
+                                  ctx->tile_list, nb, ra, s);
+        }
+        if (ctx->prof) HIPCHK(hipEventRecord(ctx->pev[1], s));
+        HIPCHK(hipGetLastError());
+        int rc = read_scalars(ctx, 0, out);
+        if (rc) return rc;
+        // launch kidx performs iteration kidx - 1; a stop inside the chunk
+        // leaves no-op launches in the bracket, so such chunks are not timed
+        if (ctx->prof && !out->done) {
+            ctx->prof_apply_ms += elapsed(ctx->pev[0], ctx->pev[1]) / (chunk - 1);
+            ++ctx->prof_apply_n;
+        }
+        if (out->done) return VFS_OK;
+        chunk = std::min(chunk * 2, 256);
+    }
+}
+
 // Truncated flexible CG (kFcgMax previous directions) with the learned
 // two-level preconditioner (3D, FP32): z = a1 D^-1 r + w network(r1) from the
 // (r.D^-1 r, r.r) partials of the previous kernel (net_precond), then the
@@ -190,7 +232,7 @@ int run_chunks_fcg(vfs_ctx* ctx, Vecs<float>& v, bool set_bb, Scalars* out) {
     const Parts P = parts(ctx);
     vfs_unet* u = ctx->net;
     hipStream_t s = ctx->stream;
-    const int nbA = apply_blocks(g, ctx->tiles), nbU = update_blocks(g, ctx->tiles);
+    const int nbA = apply_blocks(g, ctx->tiles, 4), nbU = update_blocks(g, ctx->tiles);
     const int nbV = vec_grid_blocks(g), nbZ = coarse_blocks(g);
     const int* skip = &ctx->sc->done;
     constexpr int R = kFcgMax + 1;
@@ -247,19 +289,24 @@ int true_residual(vfs_ctx* ctx, const double* b, const double* x, Scalars* so) {
     const RedArgs rr{ctx->sc + 1, nullptr, 0, P.R, 0, 0};
     launch_apply<double>(g, ctx->tiles, MODE_RESID, false, nullptr, nullptr, nullptr, x, nullptr,
                          ctx->r, ctx->a, ctx->c, ctx->K, b, rr, ctx->stream);
-    launch_finalize(P.R, apply_blocks(g, ctx->tiles), 1, ctx->sc + 1, 0, ctx->stream);
+    launch_finalize(P.R, apply_blocks(g, ctx->tiles, 8), 1, ctx->sc + 1, 0, ctx->stream);
     HIPCHK(hipGetLastError());
     return read_scalars(ctx, 1, so);
 }
 
 // direction buffers and q start at zero (tiles that stay inactive are never
-// written by the 3D kernels, and their halo values are read)
+// written by the 3D kernels or the fused 2D kernel, and their halo values are
+// read; the active tiles can change from one assembly to the next)
 int zero_dirs(vfs_ctx* ctx, bool f32) {
     const size_t n = (size_t)ctx->g.nsamp() * ctx->g.NP;
     if (f32) {
         HIPCHK(hipMemsetAsync(ctx->p032, 0, n * sizeof(float), ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->p132, 0, n * sizeof(float), ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->q32, 0, n * sizeof(float), ctx->stream));
+        if (ctx->g.dim == 2) {   // second r and q buffers of the fused 2D CG
+            HIPCHK(hipMemsetAsync(ctx->z32, 0, n * sizeof(float), ctx->stream));
+            HIPCHK(hipMemsetAsync(ctx->f32b, 0, n * sizeof(float), ctx->stream));
+        }
     } else {
         HIPCHK(hipMemsetAsync(ctx->p0, 0, n * sizeof(double), ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->p1, 0, n * sizeof(double), ctx->stream));
@@ -353,7 +400,12 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
                               ctx->max_iter - total, ctx->sc, P.B, ctx->stream);
         HIPCHK(hipGetLastError());
         Scalars s{};
-        rc = learned ? run_chunks_fcg(ctx, v, true, &s) : run_chunks<float>(ctx, v, true, &s);
+        if (learned)
+            rc = run_chunks_fcg(ctx, v, true, &s);
+        else if (g.dim == 2)
+            rc = run_chunks_fused(ctx, true, &s);
+        else
+            rc = run_chunks<float>(ctx, v, true, &s);
         if (rc) return rc;
         total += s.iter;
         fallbacks += s.fallbacks;
@@ -421,6 +473,13 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
                            ctx->rhof, ctx->K, ctx->fflag, s);
         launch_sample_coef3d(g, ctx->WL, ctx->WF, ctx->mu, ctx->K, ctx->fflag, ctx->ustar,
                              ctx->ubc, ctx->a, ctx->c, ctx->dinv, ctx->b, ctx->sc, s);
+    }
+    if (g.dim == 2) {
+        launch_tiles2d(g, ctx->a, ctx->tile_flags, ctx->tile_list, ctx->tile_count, s);
+        HIPCHK(hipMemcpyAsync(ctx->tile_count_host, ctx->tile_count, sizeof(int),
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ctx->tiles2d = *ctx->tile_count_host;
     }
     if (g.dim == 3) {
         launch_tiles(g, ctx->a, ctx->tile_flags, ctx->tile_list, ctx->tile_count, s);
@@ -558,7 +617,8 @@ int vfs_destroy(vfs_ctx* ctx) {
                     ctx->K32,   ctx->a32,   ctx->c32,  ctx->dinv32, ctx->x,      ctx->r,
                     ctx->p0,    ctx->p1,    ctx->q,    ctx->z,      ctx->x32,    ctx->r32,
                     ctx->p032,  ctx->p132,  ctx->q32,  ctx->z32,    ctx->partials, ctx->counter,
-                    ctx->sc,    ctx->flag,  ctx->stage, ctx->netvec, ctx->netpart, ctx->netcoef};
+                    ctx->sc,    ctx->flag,  ctx->stage, ctx->netvec, ctx->netpart, ctx->netcoef,
+                    ctx->f32b,  ctx->fpart};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->tile_flags) (void)hipFree(ctx->tile_flags);
@@ -631,6 +691,13 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
     ALLOC(ctx->p132, ns * NP);
     ALLOC(ctx->q32, ns * NP);
     ALLOC(ctx->z32, ns * NP);
+    int ntx2 = 0, nty2 = 0;
+    if (dim == 2) fused2d_tile_dims(g, ntx2, nty2);
+    const long long nt2 = (long long)ntx2 * nty2;
+    if (dim == 2) {
+        ALLOC(ctx->f32b, ns * NP);
+        ALLOC(ctx->fpart, 10 * nt2 + 64);
+    }
     ctx->capA = apply_grid_blocks(g) + 16;
     ctx->capB = std::max(apply_grid_blocks(g), vec_grid_blocks(g)) + 16;
     ALLOC(ctx->partials, 2 * ctx->capA + 2 * ctx->capB + 64);
@@ -644,6 +711,10 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
         const long long nt = (long long)ctx->tiles.ntx * ctx->tiles.nty * ctx->tiles.ntz;
         ALLOC(ctx->tile_flags, nt);
         ALLOC(ctx->tile_list, nt);
+        ALLOC(ctx->tile_count, 4);
+    } else {
+        ALLOC(ctx->tile_flags, nt2);
+        ALLOC(ctx->tile_list, nt2);
         ALLOC(ctx->tile_count, 4);
     }
 #undef ALLOC

@@ -83,6 +83,15 @@ struct Scalars {
     double pqh[8];      // p.Ap of iteration k in slot k & 7 (truncated flexible CG)
 };
 
+// Vectors of the fused 2D CG (one launch per iteration): x in place; r, p
+// and q = A p double-buffered by launch parity.
+struct FusedVecs {
+    void* x;
+    void* r[2];
+    void* p[2];
+    void* q[2];
+};
+
 // Truncated flexible CG: the m previous directions P_i and their images
 // Q_i = A P_i (i = 1 most recent), mk of them valid.
 constexpr int kFcgMax = 4;
@@ -171,6 +180,8 @@ struct vfs_ctx {
     float* p132 = nullptr;
     float* q32 = nullptr;
     float* z32 = nullptr;
+    float* f32b = nullptr;       // 2D: second q buffer of the fused CG
+    double* fpart = nullptr;     // 2D: its two 5-value partial regions
 
     // reductions
     double* partials = nullptr;  // per-workgroup partial sums: regions A, B, R
@@ -191,6 +202,7 @@ struct vfs_ctx {
     int* tile_count = nullptr;
     int* tile_count_host = nullptr;  // pinned
     vfs::Tiles tiles{nullptr, 0, 0, 0, 0};
+    int tiles2d = 0;                 // 2D: active tiles of the fused CG (in tile_list)
 
     bool assembled = false;
     double dt_assembled = 0.0;
@@ -263,7 +275,17 @@ enum ApplyMode { MODE_DIR = 0, MODE_APPLY = 1, MODE_RESID = 2, MODE_FDIR = 3, MO
 int apply_grid_blocks(const Geo& g);   // 2D apply grid / all 3D tiles (capacity)
 int vec_grid_blocks(const Geo& g);     // dense pointwise kernels
 // workgroups of one apply / update launch (the partial count they write)
-int apply_blocks(const Geo& g, const Tiles& tl);
+// workgroups (= partials) of an apply launch on T = float (word 4) or double (8)
+int apply_blocks(const Geo& g, const Tiles& tl, int word);
+int apply3d_grid(int count, int word);
+// fused 2D CG over the compacted list of tiles holding an active sample
+void fused2d_tile_dims(const Geo& g, int& ntx, int& nty);
+void launch_tiles2d(const Geo& g, const double* a, int* flags, int* list, int* count,
+                    hipStream_t s);
+template <typename T>
+void launch_fused2d(const Geo& g, bool init, const FusedVecs& v, const T* dinv, const T* a,
+                    const T* c, const T* K, const int* tiles, int count, const RedArgs& ra,
+                    hipStream_t s);
 int update_blocks(const Geo& g, const Tiles& tl);
 template <typename T>
 void launch_apply(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,

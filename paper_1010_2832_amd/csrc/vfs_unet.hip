@@ -265,7 +265,7 @@ int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, co
     float* R1 = D + 2 * n;
     float* NV = D + 3 * n;
     float* QN = D + 4 * n;
-    const int nbA = apply_blocks(g, ctx->tiles);
+    const int nbA = apply_blocks(g, ctx->tiles, 4);
     // Jacobi step: d = D^-1 r, A d
     const RedArgs j1{ctx->sc, nullptr, 0, net_region(ctx, 0), 0, 0, nullptr, 0, skip};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, false, r, nullptr, dinv, nullptr, D, QD, a, c, K,
@@ -539,7 +539,7 @@ int vfs_unet_train_step(vfs_unet* u, vfs_ctx* ctx, const double* r, const double
     float* R1 = D + 2 * n;
     float* NV = D + 3 * n;
     float* QN = D + 4 * n;
-    const int nbA = apply_blocks(g, ctx->tiles);
+    const int nbA = apply_blocks(g, ctx->tiles, 4);
     // Jacobi step on (r, e): r1 = r - a1 A d, e1 = e - a1 d (FP64 copies in ctx->r, ctx->z)
     launch_net_rdr(g, ctx->r32, ctx->dinv32, u->dpart, s);
     const RedArgs j1{ctx->sc, nullptr, 0, net_region(ctx, 0), 0, 0, nullptr, 0, nullptr};
