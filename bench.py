@@ -95,6 +95,50 @@ def cpu_baseline(case, iters, seconds_cap=30.0):
             "assembly_s": t1 - t0}
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96.npy")
+
+
+def config5_leg(V, learned_cap=400):
+    """Learned vs plain PCG on the 3D 256^3 configuration: Jacobi PCG in mixed
+    precision to 1e-6, then truncated flexible CG with the committed network
+    (capped at learned_cap iterations to bound the run) on the same step."""
+    import numpy as np
+    import cases
+    case = cases.config5()
+    ctx = V.context_from_case(case, precision=V.VFS_MIXED, tol=1e-6)
+    out = {"workload": "3D 256^3 pool (depth 0.3) + 8 spheres + moving solid sphere, mu log-uniform "
+                       "[1,1000] smooth, rho [0.5,2], g (0,-9.8,0), dt 1e-3, seed 5, mixed to 1e-6"}
+    ctx.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_MIXED, 1e-6, 200000)
+    ctx.vfs_set_profiling(True)
+    ctx.vfs_step(case["dt"])
+    st = ctx.vfs_get_stats()
+    out["plain_jacobi_pcg"] = {
+        "iterations": st["iterations"], "solve_ms": st["t_solve_ms"], "step_ms": st["t_step_ms"],
+        "rel_residual_fp64": st["rel_residual"], "n_active": st["n_active"],
+        "dof_iter_per_s": st["n_active"] * st["iterations"] / (st["t_solve_ms"] * 1e-3),
+        "ms_per_iteration": st["t_solve_ms"] / max(1, st["iterations"]),
+        "apply_avg_ms": st["t_apply_avg_ms"], "update_avg_ms": st["t_update_avg_ms"]}
+    if os.path.exists(WEIGHTS):
+        net = V.Unet()
+        net.vfs_unet_set_weights(np.load(WEIGHTS, allow_pickle=False).astype(np.float32))
+        ctx.vfs_set_preconditioner(net)
+        ctx.vfs_set_solver(V.VFS_PRECOND_LEARNED, V.VFS_MIXED, 1e-6, learned_cap)
+        ctx.vfs_set_velocity(case["u"])
+        ctx.vfs_set_profiling(True)
+        ctx.vfs_step(case["dt"], allow_unconverged=True)
+        sl = ctx.vfs_get_stats()
+        out["learned_fcg"] = {
+            "weights": os.path.relpath(WEIGHTS, ROOT), "iteration_cap": learned_cap,
+            "iterations": sl["iterations"], "solve_ms": sl["t_solve_ms"],
+            "rel_residual_fp64": sl["rel_residual"], "converged": sl["rel_residual"] <= 1e-6,
+            "ms_per_iteration": sl["t_solve_ms"] / max(1, sl["iterations"]),
+            "precond_avg_ms": sl["t_precond_avg_ms"], "fallbacks": sl["precond_fallbacks"]}
+        ctx.vfs_set_preconditioner(None)
+        net.close()
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +151,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--cpu-iters", type=int, default=400)
+    ap.add_argument("--no-config5", action="store_true",
+                    help="skip the 256^3 learned-vs-plain leg")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -215,6 +261,8 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
     ctx.close()
+    if not args.no_config5:
+        out["config5_learned_vs_plain"] = config5_leg(V)
     print(json.dumps(out), flush=True)
 
 

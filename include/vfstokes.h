@@ -112,6 +112,12 @@ typedef struct vfs_stats {
     double  t_precond_avg_ms;
     int32_t precond_fallbacks;
     int32_t pad0;
+    /* sample positions the solver kernels sweep: active tiles (tiles holding
+       an active sample) x anchors per tile x sample types, counting positions
+       past the grid edge; the solver vectors are zero outside these tiles.
+       Set by assembly.  In 2D it describes the VFS_MIXED (fused) solve; the
+       2D VFS_FP64 kernels sweep the whole grid. */
+    int64_t n_tile_samples;
 } vfs_stats;
 
 /* Last error message of a context (or of the failed create when ctx is NULL). */

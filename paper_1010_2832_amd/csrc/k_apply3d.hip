@@ -304,6 +304,213 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
     block_partial<1, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
 }
 
+// MODE_DIR (Jacobi PCG direction + apply) with software pipelining: the raw
+// inputs (r, D^-1, p_old, a) of plane k+2 are loaded into registers while
+// plane k's faces and outputs are computed, and the face K and output c
+// values one plane ahead, so no plane waits for a full memory round trip.
+// Same arithmetic, same order and same partials as k_apply3d<T, MODE_DIR>.
+template <typename T>
+struct RawPlane {
+    T r[6], d[6], p[6], a[6];
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __restrict__ r,
+                                                   const T* __restrict__ dinv,
+                                                   const T* __restrict__ pin, T* __restrict__ pout,
+                                                   T* __restrict__ q, const T* __restrict__ a,
+                                                   const T* __restrict__ c,
+                                                   const T* __restrict__ K, RedArgs ra) {
+    if (ra.sc->done) return;
+    double bd;
+    if (!cg_direction_preamble<NT>(ra, blockIdx.x, bd)) return;
+    const bool first = ra.kidx == 0;
+    const T beta = (T)bd;
+    __shared__ T sW[2][6][HY][HX];
+    __shared__ T gU[2][FY][FX];
+    __shared__ T gV[2][FY][FX];
+    __shared__ T gW[2][FY][FX];
+    const long long NP = g.NP;
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    // this thread's halo-ring position (rows lj = 0 and HY-1, columns li = 0 and HX-1)
+    const bool hrole = tid < 2 * HX + 2 * TY;
+    int hli = 0, hlj = 0;
+    if (tid < HX) {
+        hli = tid;
+        hlj = 0;
+    } else if (tid < 2 * HX) {
+        hli = tid - HX;
+        hlj = HY - 1;
+    } else if (hrole) {
+        const int e = tid - 2 * HX;
+        hlj = 1 + (e >> 1);
+        hli = (e & 1) ? HX - 1 : 0;
+    }
+    constexpr int NF = (FX * FY + NT - 1) / NT;
+    double acc = 0.0;
+    const TileRange trg = tile_range(tl.count);
+    for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
+        int i0, j0, k0;
+        tile_origin(tl, wtile, i0, j0, k0);
+        const int kend = min(k0 + KZ, g.nz + 1);
+        const int io = i0 + tx, jo = j0 + ty;
+        const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
+
+        auto fetch = [&](int kk, RawPlane<T>& o, RawPlane<T>& h) {
+            const bool ino = io <= g.nx + 1 && jo <= g.ny + 1 && kk <= g.nz + 1;
+            const long long oo = ino ? g.idx(io, jo, kk) : 0;
+            const bool inh = hrole && ih <= g.nx + 1 && jh <= g.ny + 1 && kk <= g.nz + 1;
+            const long long oh = inh ? g.idx(ih, jh, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const long long so = oo + s * NP, sh = oh + s * NP;
+                o.r[s] = ino ? r[so] : T(0);
+                o.d[s] = ino ? dinv[so] : T(0);
+                o.p[s] = (ino && !first) ? pin[so] : T(0);
+                o.a[s] = ino ? a[so] : T(0);
+                h.r[s] = inh ? r[sh] : T(0);
+                h.d[s] = inh ? dinv[sh] : T(0);
+                h.p[s] = (inh && !first) ? pin[sh] : T(0);
+                h.a[s] = inh ? a[sh] : T(0);
+            }
+        };
+        // direction values of plane kk into the ring slot; own anchor values out
+        auto commit = [&](int kk, const RawPlane<T>& o, const RawPlane<T>& h, T (&vo)[6],
+                          T (&ao)[6]) {
+            const int sl = kk & 1;
+            const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
+            const long long oo = own ? g.idx(io, jo, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const T z = o.d[s] * o.r[s];
+                const T val = first ? z : z + beta * o.p[s];
+                if (own) pout[oo + s * NP] = val;
+                vo[s] = val;
+                ao[s] = o.a[s];
+                sW[sl][s][ty + 1][tx + 1] = o.a[s] * val;
+            }
+            if (hrole) {
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    const T z = h.d[s] * h.r[s];
+                    const T val = first ? z : z + beta * h.p[s];
+                    sW[sl][s][hlj][hli] = h.a[s] * val;
+                }
+            }
+        };
+        // K of the faces formed at plane kk: u, v at kk and w at kk + 1
+        auto fetchK = [&](int kk, T (&ku)[NF], T (&kv)[NF], T (&kw)[NF]) {
+#pragma unroll
+            for (int m = 0; m < NF; ++m) {
+                const int e = tid + m * NT;
+                const int li = e % FX, lj = e / FX;
+                ku[m] = kv[m] = kw[m] = T(0);
+                if (e < FX * FY) {
+                    const int iu = i0 + li, ju = j0 - 1 + lj;
+                    if (iu <= g.nx && ju >= 0 && ju < g.ny && kk >= 0 && kk < g.nz)
+                        ku[m] = K[g.idx(iu, ju, kk)];
+                    const int iv = i0 - 1 + li, jv = j0 + lj;
+                    if (iv >= 0 && iv < g.nx && jv <= g.ny && kk >= 0 && kk < g.nz)
+                        kv[m] = K[NP + g.idx(iv, jv, kk)];
+                    const int iw = i0 - 1 + li, jw = j0 - 1 + lj, kw2 = kk + 1;
+                    if (iw >= 0 && iw < g.nx && jw >= 0 && jw < g.ny && kw2 >= 0 && kw2 <= g.nz)
+                        kw[m] = K[2 * NP + g.idx(iw, jw, kw2)];
+                }
+            }
+        };
+        auto faces = [&](int kk, const T (&ku)[NF], const T (&kv)[NF], const T (&kw)[NF]) {
+            const int s0 = kk & 1, s1 = (kk + 1) & 1;
+#pragma unroll
+            for (int m = 0; m < NF; ++m) {
+                const int e = tid + m * NT;
+                if (e >= FX * FY) continue;
+                const int li = e % FX, lj = e / FX;
+                gU[s0][lj][li] = ku[m] * ((sW[s0][0][lj][li + 1] - sW[s0][0][lj][li]) +
+                                          (sW[s0][1][lj][li] - sW[s0][1][lj][li + 1]) +
+                                          (sW[s0][3][lj][li + 1] - sW[s0][3][lj + 1][li + 1]) +
+                                          (sW[s0][4][lj][li + 1] - sW[s1][4][lj][li + 1]));
+                gV[s0][lj][li] = kv[m] * ((sW[s0][0][lj + 1][li] - sW[s0][0][lj][li]) +
+                                          (sW[s0][2][lj][li] - sW[s0][2][lj + 1][li]) +
+                                          (sW[s0][3][lj + 1][li] - sW[s0][3][lj + 1][li + 1]) +
+                                          (sW[s0][5][lj + 1][li] - sW[s1][5][lj + 1][li]));
+                gW[s1][lj][li] = kw[m] * ((sW[s1][0][lj][li] - sW[s0][0][lj][li]) +
+                                          (sW[s1][1][lj][li] - sW[s0][1][lj][li]) +
+                                          (sW[s1][2][lj][li] - sW[s0][2][lj][li]) +
+                                          (sW[s1][4][lj][li] - sW[s1][4][lj][li + 1]) +
+                                          (sW[s1][5][lj][li] - sW[s1][5][lj + 1][li]));
+            }
+        };
+        auto fetchC = [&](int kk, T (&cc)[5]) {
+            const bool ok = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
+            const long long o = ok ? g.idx(io, jo, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) cc[s] = ok ? c[(s + 1) * NP + o] : T(0);
+        };
+
+        T vcur[6], acur[6], vnext[6], anext[6];
+        RawPlane<T> Fo, Fh;
+        T Ku[NF], Kv[NF], Kw[NF], Cc[5];
+        __syncthreads();   // LDS of the previous tile is no longer read
+        // prologue: planes k0-1 and k0, faces at k0-1
+        fetch(k0 - 1, Fo, Fh);
+        fetchK(k0 - 1, Ku, Kv, Kw);
+        commit(k0 - 1, Fo, Fh, vnext, anext);
+        fetch(k0, Fo, Fh);
+        commit(k0, Fo, Fh, vcur, acur);
+        fetch(k0 + 1, Fo, Fh);            // in flight during the prologue faces
+        __syncthreads();
+        faces(k0 - 1, Ku, Kv, Kw);
+        fetchK(k0, Ku, Kv, Kw);
+        fetchC(k0, Cc);
+        __syncthreads();
+
+        for (int k = k0; k < kend; ++k) {
+            commit(k + 1, Fo, Fh, vnext, anext);
+            if (k + 2 <= kend) fetch(k + 2, Fo, Fh);
+            __syncthreads();
+            faces(k, Ku, Kv, Kw);
+            T Cn[5];
+            fetchK(k + 1, Ku, Kv, Kw);
+            fetchC(k + 1, Cn);
+            __syncthreads();
+            if (io <= g.nx && jo <= g.ny) {
+                const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;
+                const T gu0 = gU[sk][ty + 1][tx], gu1 = gU[sk][ty + 1][tx + 1];
+                const T gum = gU[sk][ty][tx], guz = gU[sp][ty + 1][tx];
+                const T gv0 = gV[sk][ty][tx + 1], gv1 = gV[sk][ty + 1][tx + 1];
+                const T gvm = gV[sk][ty][tx], gvz = gV[sp][ty][tx + 1];
+                const T gw0 = gW[sk][ty + 1][tx + 1], gw1 = gW[sn][ty + 1][tx + 1];
+                const T gwx = gW[sk][ty + 1][tx], gwy = gW[sk][ty][tx + 1];
+                const long long o = g.idx(io, jo, k);
+                const T c1 = Cc[0], c2 = Cc[1];
+                const T cross = T(0.5) * fmin(c1, c2);
+                T y[6];
+                y[0] = acur[0] * ((gu0 - gu1) + (gv0 - gv1) + (gw0 - gw1));
+                y[1] = acur[1] * ((gu1 - gu0) + (gw0 - gw1)) + c1 * vcur[1] + cross * vcur[2];
+                y[2] = acur[2] * ((gv1 - gv0) + (gw0 - gw1)) + c2 * vcur[2] + cross * vcur[1];
+                y[3] = acur[3] * ((gu0 - gum) + (gv0 - gvm)) + Cc[2] * vcur[3];
+                y[4] = acur[4] * ((gu0 - guz) + (gw0 - gwx)) + Cc[3] * vcur[4];
+                y[5] = acur[5] * ((gv0 - gvz) + (gw0 - gwy)) + Cc[4] * vcur[5];
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    q[s * NP + o] = y[s];
+                    acc += (double)vcur[s] * (double)y[s];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                vcur[s] = vnext[s];
+                acur[s] = anext[s];
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) Cc[s] = Cn[s];
+        }
+    }
+    double vv[1] = {acc};
+    block_partial<1, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
+}
+
 // x += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r over the active tiles
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict__ x,
@@ -421,19 +628,30 @@ void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* cou
 // Workgroups of a 3D apply launch: no more than can be resident at once
 // (occupancy x compute units, queried once per device and precision), so no
 // tail wave runs after the first, and at most kMaxTileBlocks.
+int tile3d_anchors() { return TX * TY * KZ; }
+
 int apply3d_grid(int count, int word) {
     static int cache[2][16] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     int& c = cache[word == 8 ? 1 : 0][dev & 15];
     if (c == 0) {
-        int nb = 0, ncu = 0;
+        // the lower occupancy of the generic and the pipelined kernel: every
+        // 3D apply of one precision uses the same grid, so its partial count
+        // is known to the consumer
+        int nb = 0, nb2 = 0, ncu = 0;
         const hipError_t e =
             word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &nb, k_apply3d<double, MODE_DIR, false>, NT, 0)
+                            &nb, k_apply3d<double, MODE_DIR, true>, NT, 0)
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &nb, k_apply3d<float, MODE_DIR, false>, NT, 0);
-        if (e != hipSuccess || nb < 1) nb = 1;
+                            &nb, k_apply3d<float, MODE_DIR, true>, NT, 0);
+        const hipError_t e2 =
+            word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_dir3d_pipe<double>,
+                                                                     NT, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_dir3d_pipe<float>,
+                                                                     NT, 0);
+        if (e != hipSuccess || e2 != hipSuccess) nb = 1;
+        nb = std::max(1, std::min(nb, nb2));
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             ncu < 1)
             ncu = 1;
@@ -453,8 +671,8 @@ void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* 
             hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                                dinv, pin, pout, q, a, c, K, bvec, ra);
         else
-            hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
-                               dinv, pin, pout, q, a, c, K, bvec, ra);
+            hipLaunchKernelGGL((k_dir3d_pipe<T>), gs, dim3(NT), 0, s, g, tl, r, dinv, pin, pout,
+                               q, a, c, K, ra);
     } else if (mode == MODE_FDIR) {
         hipLaunchKernelGGL((k_apply3d<T, MODE_FDIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                            dinv, pin, pout, q, a, c, K, bvec, ra);

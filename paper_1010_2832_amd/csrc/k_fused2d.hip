@@ -286,6 +286,8 @@ constexpr int kBX = 64, kBY = 8;
 
 }  // namespace
 
+int tile2d_anchors() { return kBX * kBY; }
+
 void fused2d_tile_dims(const Geo& g, int& ntx, int& nty) {
     ntx = (g.nx + 1 + kBX - 1) / kBX;
     nty = (g.ny + 1 + kBY - 1) / kBY;

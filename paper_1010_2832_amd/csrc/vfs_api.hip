@@ -480,6 +480,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         ctx->tiles2d = *ctx->tile_count_host;
+        ctx->stats.n_tile_samples = (int64_t)ctx->tiles2d * tile2d_anchors() * g.nsamp();
     }
     if (g.dim == 3) {
         launch_tiles(g, ctx->a, ctx->tile_flags, ctx->tile_list, ctx->tile_count, s);
@@ -488,6 +489,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         HIPCHK(hipStreamSynchronize(s));
         ctx->tiles.list = ctx->tile_list;
         ctx->tiles.count = *ctx->tile_count_host;
+        ctx->stats.n_tile_samples = (int64_t)ctx->tiles.count * tile3d_anchors() * g.nsamp();
     }
     if (ctx->precision == VFS_MIXED) {
         const long long ns = (long long)g.nsamp() * g.NP, nf = (long long)g.dim * g.NP;

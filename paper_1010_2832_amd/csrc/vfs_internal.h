@@ -278,6 +278,9 @@ int vec_grid_blocks(const Geo& g);     // dense pointwise kernels
 // workgroups (= partials) of an apply launch on T = float (word 4) or double (8)
 int apply_blocks(const Geo& g, const Tiles& tl, int word);
 int apply3d_grid(int count, int word);
+// anchor positions of one tile of the 3D kernels and of the fused 2D kernel
+int tile3d_anchors();
+int tile2d_anchors();
 // fused 2D CG over the compacted list of tiles holding an active sample
 void fused2d_tile_dims(const Geo& g, int& ntx, int& nty);
 void launch_tiles2d(const Geo& g, const double* a, int* flags, int* list, int* count,

@@ -1,6 +1,7 @@
 """Compare Jacobi PCG with flexible CG and the learned preconditioner.
 
     python -m paper_1010_2832_amd.eval_precond --weights W.npy 64:143:6000 256:5:3000
+    python -m paper_1010_2832_amd.eval_precond --solvers jacobi 256:5:200
 
 Each argument is n:seed:max_iter for a seeded 3D pool problem (seed 5 with
 n = 256 is the 256^3 benchmark configuration).  Both solvers run the full
@@ -23,7 +24,9 @@ if ROOT not in sys.path:
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--weights", required=True)
+    ap.add_argument("--weights", default=None, help="network weights (.npy); needed for 'learned'")
+    ap.add_argument("--solvers", default="jacobi,learned",
+                    help="comma-separated subset of jacobi,learned")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("cases", nargs="+")
     a = ap.parse_args(argv)
@@ -31,14 +34,24 @@ def main(argv=None):
     import cases
     from paper_1010_2832_amd import vfstokes as V
 
-    net = V.Unet()
-    net.vfs_unet_set_weights(np.load(a.weights, allow_pickle=False).astype(np.float32))
+    solvers = [q for q in a.solvers.split(",") if q]
+    if any(q not in ("jacobi", "learned") for q in solvers):
+        ap.error(f"unknown solver in {a.solvers!r}")
+    net = None
+    if "learned" in solvers:
+        if not a.weights:
+            ap.error("--weights is required for the learned solver")
+        net = V.Unet()
+        net.vfs_unet_set_weights(np.load(a.weights, allow_pickle=False).astype(np.float32))
     for spec in a.cases:
         n, seed, cap = (int(q) for q in spec.split(":"))
         c = cases.config5(n=n) if seed == 5 else cases.pool3d(n, seed=seed)
         ctx = V.context_from_case(c, precision=V.VFS_MIXED, tol=a.tol)
-        ctx.vfs_set_preconditioner(net)
+        if net is not None:
+            ctx.vfs_set_preconditioner(net)
         for name, pc in (("jacobi", V.VFS_PRECOND_JACOBI), ("learned", V.VFS_PRECOND_LEARNED)):
+            if name not in solvers:
+                continue
             ctx.vfs_set_solver(pc, V.VFS_MIXED, a.tol, cap)
             ctx.vfs_set_velocity(c["u"])
             ctx.vfs_set_profiling(True)
@@ -47,9 +60,11 @@ def main(argv=None):
             print(f"n={n} seed={seed} {name}: {st['iterations']} it, solve {st['t_solve_ms']:.1f} ms, "
                   f"rel {st['rel_residual']:.2e}, active {st['n_active']}, apply "
                   f"{st['t_apply_avg_ms']:.3f} ms, update {st['t_update_avg_ms']:.3f} ms, precond "
-                  f"{st['t_precond_avg_ms']:.3f} ms, fallbacks {st['precond_fallbacks']}", flush=True)
+                  f"{st['t_precond_avg_ms']:.3f} ms, fallbacks {st['precond_fallbacks']}, "
+                  f"tile samples {st['n_tile_samples']}", flush=True)
         ctx.close()
-    net.close()
+    if net is not None:
+        net.close()
 
 
 if __name__ == "__main__":

@@ -29,3 +29,16 @@ def velocity_rel_linf(asm, u_gpu_flat, u_ref_flat):
 
 def oracle(case, w_min=1e-3):
     return system.step(case, w_min=w_min)
+
+
+def expected_tile_samples(asm, tile):
+    """Samples swept by the tile-list kernels: every tile (of the given anchor
+    extent) that holds an active sample, times the tile's anchors, times the
+    sample types; a sample of any type anchored at array index (i, j[, k])
+    belongs to tile (i // tile[0], j // tile[1][, k // tile[2]])."""
+    act = system.split_samples(asm.grid, asm.active.astype(np.float64))
+    tiles = set()
+    for name, _ in asm.grid.samples:
+        for ix in np.argwhere(act[name] > 0):
+            tiles.add(tuple(int(ix[a]) // tile[a] for a in range(len(tile))))
+    return len(tiles) * int(np.prod(tile)) * len(asm.grid.samples)

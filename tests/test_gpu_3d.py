@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import cases
-from gpu_util import flat_faces, gpu_run, oracle, velocity_rel_linf
+from gpu_util import expected_tile_samples, flat_faces, gpu_run, oracle, velocity_rel_linf
 from oracle import system
 
 pytestmark = pytest.mark.gpu
@@ -105,6 +105,8 @@ def test_step_mixed_3d(name):
     _banner(f"  iters {st['iterations']} outer {st['outer_iterations']} rel_res {st['rel_residual']:.2e} vel err {err:.2e}")
     assert st["rel_residual"] <= 1e-9
     assert err <= 1e-4
+    # the active-tile list covers exactly the 64x4x8 tiles holding an active sample
+    assert st["n_tile_samples"] == expected_tile_samples(asm, (64, 4, 8))
 
 
 def test_no_liquid_3d():
