@@ -49,7 +49,6 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     constexpr int NE2 = ((BX + 1) * (BY + 1) + NT - 1) / NT;
     const int bid = blockIdx.x;
     Scalars* sc = ra.sc;
-    if (!INIT && sc->done) return;
     const int k = ra.kidx;
     const int pin = (k + 1) & 1, pout = k & 1;   // launch k reads slot (k-1)&1, writes k&1
     const T* __restrict__ r_in = static_cast<const T*>(v.r[INIT ? 0 : pin]);
@@ -127,8 +126,12 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
         Co[rr][1] = ok ? c[2 * NP + o] : T(0);
     }
 
-    // (3) totals of iteration k-1 -> stop decision, alpha_{k-1}, beta_k
+    // (3) totals of iteration k-1 -> stop decision, alpha_{k-1}, beta_k.  The
+    // flag of a solve that has already stopped is read only now, so that its
+    // round trip overlaps the loads above (all of which are in bounds
+    // whether or not the solve goes on).
     T alpha = T(0), beta = T(0);
+    if (!INIT && sc->done) return;
     if (!INIT) {
         double t[NV];
         pl.finish(t);
