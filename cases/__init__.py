@@ -246,3 +246,37 @@ def config5(seed=5, n=256):
 def make_config(k, seed=None, **kw):
     f = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k]
     return f(**kw) if seed is None else f(seed=seed, **kw)
+
+
+# --------------------------------------------------------------------------
+# sub-box of a case (full-size checks on pieces the oracle can assemble)
+# --------------------------------------------------------------------------
+def crop(case, lo, m):
+    """The case restricted to the cells [lo[a], lo[a] + m[a]) of each axis:
+    level sets at the nodes of those cells, rho and mu at the cells, face
+    velocities and solid velocities at their faces, the origin moved to the
+    sub-box corner.  The sub-box's own boundary acts as a box wall, so only
+    quantities far enough from it agree with the full case."""
+    d = case["dim"]
+    lo = tuple(int(q) for q in lo)
+    m = tuple(int(q) for q in m)
+    for a in range(d):
+        if lo[a] < 0 or m[a] < 1 or lo[a] + m[a] > case["n"][a]:
+            raise ValueError(f"crop {lo}+{m} outside the grid {case['n']}")
+    node = tuple(slice(lo[a], lo[a] + m[a] + 1) for a in range(d))
+    cell = tuple(slice(lo[a], lo[a] + m[a]) for a in range(d))
+
+    def faces(arrs):
+        out = []
+        for ax, f in enumerate(arrs):
+            sl = tuple(slice(lo[b], lo[b] + m[b] + (1 if b == ax else 0)) for b in range(d))
+            out.append(np.array(np.asarray(f)[sl]))
+        return out
+
+    h = case["h"]
+    origin = tuple(case["origin"][a] + lo[a] * h for a in range(d))
+    return _case(d, m, h, origin, case["dt"], np.array(case["phi_l"][node]),
+                 np.array(case["phi_s"][node]), np.array(np.asarray(case["rho"])[cell]),
+                 np.array(np.asarray(case["mu"])[cell]), faces(case["u"]),
+                 None if case["u_bc"] is None else faces(case["u_bc"]), case["g"],
+                 name=f"{case.get('name', 'case')}_crop{lo}+{m}")
