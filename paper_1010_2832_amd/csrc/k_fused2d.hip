@@ -33,8 +33,19 @@
 namespace vfs {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;
 constexpr int NV = 5;   // r.z, p.q, q.D^-1 r, q.D^-1 q, r.r
+
+// Tile of workgroup b (one tile per workgroup).  Workgroups are dispatched
+// round-robin over the 8 XCDs of the chip (b runs on XCD b % 8); XCD x takes
+// the contiguous part [start_x, start_x + n_x) of the tile list, so tiles
+// that are neighbours in x share their boundary cache lines in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    if (G < 8) return b;
+    const int x = b & 7, slot = b >> 3;
+    const int q = G >> 3, rem = G & 7;
+    return x * q + min(x, rem) + slot;
+}
 
 // Launched over the compacted list of tiles that hold an active sample;
 // the vectors of the other tiles stay zero (they hold no active sample), so
@@ -64,7 +75,7 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     __shared__ T sD[3][BY + 2][BX + 2];   // D^-1
     __shared__ T sG[2][BY + 1][BX + 1];
     const long long NP = g.NP;
-    const int tile = tiles[bid];
+    const int tile = tiles[xcd_tile(bid, gridDim.x)];
     const int i0 = (tile % ntx) * BX, j0 = (tile / ntx) * BY;
     const int tid = threadIdx.x;
 
@@ -283,9 +294,10 @@ __global__ __launch_bounds__(1024) void k_tiles2d_compact(int n, const int* __re
         if (flags[t]) list[w++] = t;
 }
 
-// tile shape: 64 x 8 anchors was the fastest of 64x8, 128x4, 64x4 and 32x8 on
-// the 512^2 workload (463.7, 466.2, 481.1 and 510.0 ms per step)
-constexpr int kBX = 64, kBY = 8;
+// tile shape and workgroup size: 64 x 16 anchors with 512 threads was the
+// fastest of ten shapes and sizes on the 512^2 workload with the XCD map
+// (399.0 ms per solve against 415.7 for 64 x 8 with 256 threads)
+constexpr int kBX = 64, kBY = 16;
 
 }  // namespace
 
