@@ -627,31 +627,27 @@ void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* cou
 
 // Workgroups of a 3D apply launch: no more than can be resident at once
 // (occupancy x compute units, queried once per device and precision), so no
-// tail wave runs after the first, and at most kMaxTileBlocks.
-int tile3d_anchors() { return TX * TY * KZ; }
-
-int apply3d_grid(int count, int word) {
-    static int cache[2][16] = {};
+// tail wave runs after the first, and at most kMaxTileBlocks.  The pipelined
+// Jacobi direction kernel holds more registers than the generic kernel and
+// gets its own figure (dir3d_grid); a consumer of an apply's partials uses
+// the figure of the kernel that produced them.
+static int resident_grid(int count, int word, bool pipelined) {
+    static int cache[2][2][16] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    int& c = cache[word == 8 ? 1 : 0][dev & 15];
+    int& c = cache[pipelined ? 1 : 0][word == 8 ? 1 : 0][dev & 15];
     if (c == 0) {
-        // the lower occupancy of the generic and the pipelined kernel: every
-        // 3D apply of one precision uses the same grid, so its partial count
-        // is known to the consumer
-        int nb = 0, nb2 = 0, ncu = 0;
-        const hipError_t e =
-            word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &nb, k_apply3d<double, MODE_DIR, true>, NT, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &nb, k_apply3d<float, MODE_DIR, true>, NT, 0);
-        const hipError_t e2 =
-            word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_dir3d_pipe<double>,
-                                                                     NT, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, k_dir3d_pipe<float>,
-                                                                     NT, 0);
-        if (e != hipSuccess || e2 != hipSuccess) nb = 1;
-        nb = std::max(1, std::min(nb, nb2));
+        int nb = 0, ncu = 0;
+        hipError_t e;
+        if (pipelined)
+            e = word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dir3d_pipe<double>, NT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dir3d_pipe<float>, NT, 0);
+        else
+            e = word == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                &nb, k_apply3d<double, MODE_DIR, true>, NT, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                &nb, k_apply3d<float, MODE_DIR, true>, NT, 0);
+        if (e != hipSuccess || nb < 1) nb = 1;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             ncu < 1)
             ncu = 1;
@@ -659,6 +655,12 @@ int apply3d_grid(int count, int word) {
     }
     return std::max(1, std::min(std::min(count, kMaxTileBlocks), c));
 }
+
+int tile3d_anchors() { return TX * TY * KZ; }
+
+int apply3d_grid(int count, int word) { return resident_grid(count, word, false); }
+
+int dir3d_grid(int count, int word) { return resident_grid(count, word, true); }
 
 template <typename T>
 void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,
@@ -671,8 +673,8 @@ void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* 
             hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                                dinv, pin, pout, q, a, c, K, bvec, ra);
         else
-            hipLaunchKernelGGL((k_dir3d_pipe<T>), gs, dim3(NT), 0, s, g, tl, r, dinv, pin, pout,
-                               q, a, c, K, ra);
+            hipLaunchKernelGGL((k_dir3d_pipe<T>), dim3(dir3d_grid(tl.count, (int)sizeof(T))),
+                               dim3(NT), 0, s, g, tl, r, dinv, pin, pout, q, a, c, K, ra);
     } else if (mode == MODE_FDIR) {
         hipLaunchKernelGGL((k_apply3d<T, MODE_FDIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                            dinv, pin, pout, q, a, c, K, bvec, ra);

@@ -167,6 +167,152 @@ __global__ __launch_bounds__(CT) void k_conv3(ConvArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// 16 -> 16 channel convolution (the full-resolution layers): z-marching with
+// the input planes staged in LDS.  With 16 output channels a voxel operand
+// feeds a single MFMA, so operand bandwidth bounds the layer; here each input
+// plane is read from global memory once per tile (plus its x,y halo) and the
+// 27 taps read their operands from LDS, while the 14 weight operands of a
+// lane stay in registers for the whole launch.
+//
+// Workgroup: a 32 x 8 voxel tile in x,y marching Z16 planes in z.  LDS holds
+// a ring of 4 input planes of 34 x 10 voxels, each split into two arrays of 8
+// channels (16 bytes per voxel, so the 16 lanes of one MFMA column group read
+// 256 contiguous bytes).  Step z: issue the global loads of plane z+2,
+// compute output plane z from the planes z-1, z, z+1, write the epilogue,
+// store plane z+2 into its slot (which held plane z-2), one barrier.
+// K = 32 kc + 8 kq + j covers taps t = 2 kc + kq / 2 with channels
+// 8 (kq % 2) + j, so the lanes 0-31 of a wave read one tap and lanes 32-63
+// the next; tap 27 (kc = 13, kq >= 2) is the zero padding of K.
+// ---------------------------------------------------------------------------
+constexpr int kZX = 32, kZY = 8, kZZ = 16;            // output tile
+constexpr int kZHX = kZX + 2, kZHY = kZY + 2;          // input plane with halo
+constexpr int kZPlane = kZHX * kZHY;                   // voxels per input plane
+constexpr int kZChunks = 2 * kZPlane;                  // 16-byte chunks per plane
+constexpr int kZLoads = (kZChunks + CT - 1) / CT;      // chunks per thread
+
+template <int EPI>
+__global__ __launch_bounds__(CT) void k_conv3_z16(ConvArgs A, int ntx, int nty, int ntz) {
+    if (A.skip && *A.skip) return;
+    constexpr int KP = conv_kp(16), NKC = KP / 32;
+    __shared__ __align__(16) uint4 sIn[4][2][kZPlane];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, n = lane & 15;
+    const Level L = A.L;
+    // XCD-contiguous tile order (workgroup b runs on XCD b % 8)
+    const int G = gridDim.x, b = blockIdx.x;
+    int tile = b;
+    if (G >= 8) {
+        const int x8 = b & 7, q = G >> 3, rem = G & 7;
+        tile = x8 * q + min(x8, rem) + (b >> 3);
+    }
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int x0 = tx * kZX, y0 = ty * kZY, z0 = tz * kZZ;
+    const int zend = min(z0 + kZZ, L.Z);
+
+    // weight operands: row co = n, K = 32 kc + 8 kq .. +7
+    bf16x8 a[NKC];
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) a[kc] = ld16(A.w + (long long)n * KP + kc * 32 + kq * 8);
+
+    // plane loader: chunk e = 2 * voxel + half of the 34 x 10 input plane
+    auto fetch = [&](int zz, uint4 (&r)[kZLoads]) {
+#pragma unroll
+        for (int m = 0; m < kZLoads; ++m) {
+            const int e = threadIdx.x + m * CT;
+            r[m] = uint4{0u, 0u, 0u, 0u};
+            if (e < kZChunks) {
+                const int v = e >> 1, h = e & 1;
+                const int x = x0 - 1 + v % kZHX, y = y0 - 1 + v / kZHX;
+                if (x <= L.X && y <= L.Y && zz <= L.Z)
+                    r[m] = *reinterpret_cast<const uint4*>(A.in + L.off(x, y, zz) * 16 + h * 8);
+            }
+        }
+    };
+    auto commit = [&](int zz, const uint4 (&r)[kZLoads]) {
+        const int sl = (zz + 4) & 3;
+#pragma unroll
+        for (int m = 0; m < kZLoads; ++m) {
+            const int e = threadIdx.x + m * CT;
+            if (e < kZChunks) sIn[sl][e & 1][e >> 1] = r[m];
+        }
+    };
+
+    uint4 pre[kZLoads];
+    fetch(z0 - 1, pre);
+    commit(z0 - 1, pre);
+    fetch(z0, pre);
+    commit(z0, pre);
+    fetch(z0 + 1, pre);
+    commit(z0 + 1, pre);
+    __syncthreads();
+
+    // this wave's four 16-voxel column groups: rows yr, x offsets xo
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
+    for (int z = z0; z < zend; ++z) {
+        const bool more = z + 2 <= zend;
+        if (more) fetch(z + 2, pre);
+        f32x4 acc[4];
+#pragma unroll
+        for (int nv = 0; nv < 4; ++nv) acc[nv] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            const int t = 2 * kc + (kq >> 1);
+            const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+            const uint4* pl = sIn[(z + dz - 1 + 4) & 3][kq & 1];
+#pragma unroll
+            for (int nv = 0; nv < 4; ++nv) {
+                const int yr = 2 * wave + (nv >> 1), xo = 16 * (nv & 1);
+                const bf16x8 bo = t < 27 ? __builtin_bit_cast(bf16x8, pl[(yr + dy) * kZHX + xo + n + dx])
+                                         : zero8;
+                acc[nv] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc], bo, acc[nv], 0, 0, 0);
+            }
+        }
+        // epilogue: lane holds output channels 4 kq .. +3 of voxel n
+#pragma unroll
+        for (int nv = 0; nv < 4; ++nv) {
+            const int yr = 2 * wave + (nv >> 1), xo = 16 * (nv & 1);
+            const int x = x0 + xo + n, y = y0 + yr;
+            if (x >= L.X || y >= L.Y) continue;
+            const int co0 = 4 * kq;
+            float o[4] = {acc[nv][0], acc[nv][1], acc[nv][2], acc[nv][3]};
+            if (EPI == EPI_F32) {
+                if (co0 < 8) {
+                    const long long v = ((long long)z * L.Y + y) * L.X + x;
+                    *reinterpret_cast<float4*>(A.out32 + v * 8 + co0) = float4{o[0], o[1], o[2], o[3]};
+                }
+                continue;
+            }
+            const long long vo = L.off(x, y, z);
+            if (EPI == EPI_RELU) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = fmaxf(o[i], 0.f);
+            } else if (EPI == EPI_MASK) {
+                const uint2 mk = *reinterpret_cast<const uint2*>(A.mask + vo * 16 + co0);
+                const uint32_t mw[4] = {mk.x & 0xffffu, mk.x >> 16, mk.y & 0xffffu, mk.y >> 16};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = bf2f(mw[i]) > 0.f ? o[i] : 0.f;
+            }
+            uint2 st;
+            st.x = f2bf(o[0]) | (f2bf(o[1]) << 16);
+            st.y = f2bf(o[2]) | (f2bf(o[3]) << 16);
+            *reinterpret_cast<uint2*>(A.out + vo * 16 + co0) = st;
+        }
+        // plane z + 2 replaces plane z - 2, which no wave reads any more
+        if (more) commit(z + 2, pre);
+        __syncthreads();
+    }
+}
+
+template <int EPI>
+void conv_launch_z16(const ConvArgs& a, hipStream_t s) {
+    const int ntx = (a.L.X + kZX - 1) / kZX, nty = (a.L.Y + kZY - 1) / kZY;
+    const int ntz = (a.L.Z + kZZ - 1) / kZZ;
+    const long long nb = (long long)ntx * nty * ntz;
+    if (nb == 0) return;
+    hipLaunchKernelGGL((k_conv3_z16<EPI>), dim3((unsigned)nb), dim3(CT), 0, s, a, ntx, nty, ntz);
+}
+
 template <int CIN, int COUT, int EPI>
 void conv_launch(const ConvArgs& a, hipStream_t s) {
     using S = ConvShape<CIN, COUT>;
@@ -729,7 +875,15 @@ bool launch_conv3(int cin, int cout, int epi, const ConvArgs& a, hipStream_t s) 
         }                                                                         \
         return false;                                                             \
     }
-    VFS_CONV(16, 16)
+    if (cin == 16 && cout == 16) {
+        switch (epi) {
+            case EPI_RELU: conv_launch_z16<EPI_RELU>(a, s); return true;
+            case EPI_PLAIN: conv_launch_z16<EPI_PLAIN>(a, s); return true;
+            case EPI_MASK: conv_launch_z16<EPI_MASK>(a, s); return true;
+            case EPI_F32: conv_launch_z16<EPI_F32>(a, s); return true;
+        }
+        return false;
+    }
     VFS_CONV(16, 32)
     VFS_CONV(32, 64)
     VFS_CONV(64, 128)

@@ -142,7 +142,8 @@ template <typename T>
 int run_chunks(vfs_ctx* ctx, Vecs<T>& v, bool set_bb, Scalars* out) {
     const Geo& g = ctx->g;
     const Parts P = parts(ctx);
-    const int nbA = apply_blocks(g, ctx->tiles, (int)sizeof(T)), nbU = update_blocks(g, ctx->tiles);
+    const int nbA = dir_apply_blocks(g, ctx->tiles, (int)sizeof(T));
+    const int nbU = update_blocks(g, ctx->tiles);
     const int nbV = vec_grid_blocks(g);
     int chunk = 8;
     int kidx = 0;

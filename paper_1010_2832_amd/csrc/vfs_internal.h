@@ -277,7 +277,11 @@ int vec_grid_blocks(const Geo& g);     // dense pointwise kernels
 // workgroups of one apply / update launch (the partial count they write)
 // workgroups (= partials) of an apply launch on T = float (word 4) or double (8)
 int apply_blocks(const Geo& g, const Tiles& tl, int word);
+// workgroups of the Jacobi-PCG direction + apply launch (MODE_DIR without a
+// given z), which in 3D runs the pipelined kernel
+int dir_apply_blocks(const Geo& g, const Tiles& tl, int word);
 int apply3d_grid(int count, int word);
+int dir3d_grid(int count, int word);
 // anchor positions of one tile of the 3D kernels and of the fused 2D kernel
 int tile3d_anchors();
 int tile2d_anchors();
