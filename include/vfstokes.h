@@ -97,10 +97,10 @@ typedef struct vfs_stats {
     /* live kernel timing (vfs_set_profiling): average device duration of one
        launch of the CG apply kernel and of the CG update kernel, from HIP
        events on the context stream around one launch of each per chunk of
-       iterations.  The 2D VFS_MIXED solve runs one fused launch per
-       iteration: t_apply_avg_ms is then its average over the back-to-back
-       launches of each chunk after the first, t_update_avg_ms is 0 and
-       n_apply_timed counts the timed chunks. */
+       iterations.  The VFS_MIXED Jacobi solve (2D and 3D) runs one fused
+       launch per iteration: t_apply_avg_ms is then its average over the
+       back-to-back launches of each chunk after the first, t_update_avg_ms
+       is 0 and n_apply_timed counts the timed chunks. */
     double  t_apply_avg_ms;
     double  t_update_avg_ms;
     int64_t n_apply_timed;

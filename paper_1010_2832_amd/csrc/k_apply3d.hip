@@ -511,6 +511,289 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
     block_partial<1, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
 }
 
+// One launch per Jacobi-PCG iteration in 3D (mixed precision), the plane-
+// marching form of the fused 2D iteration: launch k carries out iteration
+// k-1's update lazily (r_k = r_{k-1} - alpha q_{k-1} on the tile and its
+// halo, x_k = x_{k-1} + alpha p_{k-1} at the own anchors), forms z_k = D^-1 r_k
+// and p_k = z_k + beta p_{k-1}, applies q_k = A p_k and reduces (r.z, p.q,
+// q.D^-1 r, q.D^-1 q, r.r).  beta_k comes from the expansion
+// r_k.z_k = r.z - 2 alpha q.D^-1 r + alpha^2 q.D^-1 q of the previous
+// launch's totals (re-anchored every launch on the directly summed r.z), so
+// one global reduction per iteration suffices.  r, p and q alternate between
+// two buffers by launch parity because the halo of launch k reads the values
+// of launch k-1 that neighbouring workgroups overwrite.  The raw inputs of
+// plane k+2 are loaded while plane k is computed, as in k_dir3d_pipe.
+template <typename T>
+struct FusedOwn {
+    T r[6], q[6], p[6], d[6], a[6], x[6];
+};
+template <typename T>
+struct FusedHalo {
+    T r[6], q[6], p[6], d[6], a[6];
+};
+
+template <typename T, bool INIT>
+__global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
+                                                const T* __restrict__ dinv,
+                                                const T* __restrict__ a,
+                                                const T* __restrict__ c,
+                                                const T* __restrict__ K, RedArgs ra) {
+    Scalars* sc = ra.sc;
+    const int kidx = ra.kidx;
+    const int pin = (kidx + 1) & 1, pout = kidx & 1;   // launch k reads (k-1)&1, writes k&1
+    const T* __restrict__ r_in = static_cast<const T*>(v.r[INIT ? 0 : pin]);
+    const T* __restrict__ q_in = static_cast<const T*>(v.q[pin]);
+    const T* __restrict__ p_in = static_cast<const T*>(v.p[pin]);
+    T* __restrict__ r_out = static_cast<T*>(v.r[pout]);
+    T* __restrict__ p_out = static_cast<T*>(v.p[pout]);
+    T* __restrict__ q_out = static_cast<T*>(v.q[pout]);
+    T* __restrict__ x = static_cast<T*>(v.x);
+
+    // totals of the previous launch -> stop decision, alpha_{k-1}, beta_k
+    PartialLoads<5, NT, 4> pl;
+    if (!INIT) pl.load(ra.part_in, ra.nb_in);
+    if (!INIT && sc->done) return;
+    T alpha = T(0), beta = T(0);
+    if (!INIT) {
+        double t[5];
+        pl.finish(t);
+        const double rz = t[0], pq = t[1], qdr = t[2], qdq = t[3], rrk = t[4];
+        const double bb = ra.set_bb ? rrk : sc->bb;
+        int stop = 0;
+        if (!isfinite(rz) || !isfinite(rrk) || !isfinite(pq))
+            stop = 3;
+        else if (rrk <= sc->tol2 * bb)
+            stop = 1;
+        else if (kidx - 1 >= sc->max_iter)
+            stop = 2;
+        else if (!(pq > 0.0))
+            stop = 3;
+        const double ad = stop ? 0.0 : rz / pq;
+        const double rzn = rz - 2.0 * ad * qdr + ad * ad * qdq;
+        const double bd = (rz > 0.0) ? rzn / rz : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rz[kidx & 1] = rz;
+            sc->rr = rrk;
+            sc->pq = pq;
+            sc->alpha = ad;
+            sc->beta = bd;
+            if (ra.set_bb) sc->bb = bb;
+            if (stop) {
+                sc->done = stop;
+                sc->iter = kidx - 1;
+            }
+        }
+        if (stop) return;
+        alpha = (T)ad;
+        beta = (T)bd;
+    }
+
+    __shared__ T sW[2][6][HY][HX];
+    __shared__ T gU[2][FY][FX];
+    __shared__ T gV[2][FY][FX];
+    __shared__ T gW[2][FY][FX];
+    const long long NP = g.NP;
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    const bool hrole = tid < 2 * HX + 2 * TY;
+    int hli = 0, hlj = 0;
+    if (tid < HX) {
+        hli = tid;
+        hlj = 0;
+    } else if (tid < 2 * HX) {
+        hli = tid - HX;
+        hlj = HY - 1;
+    } else if (hrole) {
+        const int e = tid - 2 * HX;
+        hlj = 1 + (e >> 1);
+        hli = (e & 1) ? HX - 1 : 0;
+    }
+    constexpr int NF = (FX * FY + NT - 1) / NT;
+    double rz_n = 0.0, rr_n = 0.0, pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
+    const TileRange trg = tile_range(tl.count);
+    for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
+        int i0, j0, k0;
+        tile_origin(tl, wtile, i0, j0, k0);
+        const int kend = min(k0 + KZ, g.nz + 1);
+        const int io = i0 + tx, jo = j0 + ty;
+        const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
+
+        auto fetch = [&](int kk, FusedOwn<T>& o, FusedHalo<T>& h) {
+            const bool ino = io <= g.nx + 1 && jo <= g.ny + 1 && kk <= g.nz + 1;
+            const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
+            const long long oo = ino ? g.idx(io, jo, kk) : 0;
+            const bool inh = hrole && ih <= g.nx + 1 && jh <= g.ny + 1 && kk <= g.nz + 1;
+            const long long oh = inh ? g.idx(ih, jh, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const long long so = oo + s * NP, sh = oh + s * NP;
+                o.r[s] = ino ? r_in[so] : T(0);
+                o.d[s] = ino ? dinv[so] : T(0);
+                o.a[s] = ino ? a[so] : T(0);
+                o.q[s] = (ino && !INIT) ? q_in[so] : T(0);
+                o.p[s] = (ino && !INIT) ? p_in[so] : T(0);
+                o.x[s] = (own && !INIT) ? x[so] : T(0);
+                h.r[s] = inh ? r_in[sh] : T(0);
+                h.d[s] = inh ? dinv[sh] : T(0);
+                h.a[s] = inh ? a[sh] : T(0);
+                h.q[s] = (inh && !INIT) ? q_in[sh] : T(0);
+                h.p[s] = (inh && !INIT) ? p_in[sh] : T(0);
+            }
+        };
+        // r_k, z_k, p_k of plane kk into the ring slot; own anchors also store
+        // r_k, x_k, p_k and add to r.z, r.r; own p, a, z, D^-1 out
+        auto commit = [&](int kk, const FusedOwn<T>& o, const FusedHalo<T>& h, T (&vo)[6],
+                          T (&ao)[6], T (&zo)[6], T (&dq)[6]) {
+            const int sl = kk & 1;
+            const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
+            const long long oo = own ? g.idx(io, jo, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                const T rn = INIT ? o.r[s] : o.r[s] - alpha * o.q[s];
+                const T zn = o.d[s] * rn;
+                const T pn = INIT ? zn : zn + beta * o.p[s];
+                if (own) {
+                    const long long os = oo + s * NP;
+                    if (!INIT) {
+                        r_out[os] = rn;
+                        x[os] = o.x[s] + alpha * o.p[s];
+                    }
+                    p_out[os] = pn;
+                    rz_n += (double)rn * (double)zn;
+                    rr_n += (double)rn * (double)rn;
+                }
+                vo[s] = pn;
+                ao[s] = o.a[s];
+                zo[s] = zn;
+                dq[s] = o.d[s];
+                sW[sl][s][ty + 1][tx + 1] = o.a[s] * pn;
+            }
+            if (hrole) {
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    const T rn = INIT ? h.r[s] : h.r[s] - alpha * h.q[s];
+                    const T zn = h.d[s] * rn;
+                    const T pn = INIT ? zn : zn + beta * h.p[s];
+                    sW[sl][s][hlj][hli] = h.a[s] * pn;
+                }
+            }
+        };
+        auto fetchK = [&](int kk, T (&ku)[NF], T (&kv)[NF], T (&kw)[NF]) {
+#pragma unroll
+            for (int m = 0; m < NF; ++m) {
+                const int e = tid + m * NT;
+                const int li = e % FX, lj = e / FX;
+                ku[m] = kv[m] = kw[m] = T(0);
+                if (e < FX * FY) {
+                    const int iu = i0 + li, ju = j0 - 1 + lj;
+                    if (iu <= g.nx && ju >= 0 && ju < g.ny && kk >= 0 && kk < g.nz)
+                        ku[m] = K[g.idx(iu, ju, kk)];
+                    const int iv = i0 - 1 + li, jv = j0 + lj;
+                    if (iv >= 0 && iv < g.nx && jv <= g.ny && kk >= 0 && kk < g.nz)
+                        kv[m] = K[NP + g.idx(iv, jv, kk)];
+                    const int iw = i0 - 1 + li, jw = j0 - 1 + lj, kw2 = kk + 1;
+                    if (iw >= 0 && iw < g.nx && jw >= 0 && jw < g.ny && kw2 >= 0 && kw2 <= g.nz)
+                        kw[m] = K[2 * NP + g.idx(iw, jw, kw2)];
+                }
+            }
+        };
+        auto faces = [&](int kk, const T (&ku)[NF], const T (&kv)[NF], const T (&kw)[NF]) {
+            const int s0 = kk & 1, s1 = (kk + 1) & 1;
+#pragma unroll
+            for (int m = 0; m < NF; ++m) {
+                const int e = tid + m * NT;
+                if (e >= FX * FY) continue;
+                const int li = e % FX, lj = e / FX;
+                gU[s0][lj][li] = ku[m] * ((sW[s0][0][lj][li + 1] - sW[s0][0][lj][li]) +
+                                          (sW[s0][1][lj][li] - sW[s0][1][lj][li + 1]) +
+                                          (sW[s0][3][lj][li + 1] - sW[s0][3][lj + 1][li + 1]) +
+                                          (sW[s0][4][lj][li + 1] - sW[s1][4][lj][li + 1]));
+                gV[s0][lj][li] = kv[m] * ((sW[s0][0][lj + 1][li] - sW[s0][0][lj][li]) +
+                                          (sW[s0][2][lj][li] - sW[s0][2][lj + 1][li]) +
+                                          (sW[s0][3][lj + 1][li] - sW[s0][3][lj + 1][li + 1]) +
+                                          (sW[s0][5][lj + 1][li] - sW[s1][5][lj + 1][li]));
+                gW[s1][lj][li] = kw[m] * ((sW[s1][0][lj][li] - sW[s0][0][lj][li]) +
+                                          (sW[s1][1][lj][li] - sW[s0][1][lj][li]) +
+                                          (sW[s1][2][lj][li] - sW[s0][2][lj][li]) +
+                                          (sW[s1][4][lj][li] - sW[s1][4][lj][li + 1]) +
+                                          (sW[s1][5][lj][li] - sW[s1][5][lj + 1][li]));
+            }
+        };
+        auto fetchC = [&](int kk, T (&cc)[5]) {
+            const bool ok = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
+            const long long o = ok ? g.idx(io, jo, kk) : 0;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) cc[s] = ok ? c[(s + 1) * NP + o] : T(0);
+        };
+
+        T vcur[6], acur[6], zcur[6], dcur[6], vnext[6], anext[6], znext[6], dnext[6];
+        FusedOwn<T> Fo;
+        FusedHalo<T> Fh;
+        T Ku[NF], Kv[NF], Kw[NF], Cc[5];
+        __syncthreads();   // LDS of the previous tile is no longer read
+        fetch(k0 - 1, Fo, Fh);
+        fetchK(k0 - 1, Ku, Kv, Kw);
+        commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext);
+        fetch(k0, Fo, Fh);
+        commit(k0, Fo, Fh, vcur, acur, zcur, dcur);
+        fetch(k0 + 1, Fo, Fh);
+        __syncthreads();
+        faces(k0 - 1, Ku, Kv, Kw);
+        fetchK(k0, Ku, Kv, Kw);
+        fetchC(k0, Cc);
+        __syncthreads();
+
+        for (int k = k0; k < kend; ++k) {
+            commit(k + 1, Fo, Fh, vnext, anext, znext, dnext);
+            if (k + 2 <= kend) fetch(k + 2, Fo, Fh);
+            __syncthreads();
+            faces(k, Ku, Kv, Kw);
+            T Cn[5];
+            fetchK(k + 1, Ku, Kv, Kw);
+            fetchC(k + 1, Cn);
+            __syncthreads();
+            if (io <= g.nx && jo <= g.ny) {
+                const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;
+                const T gu0 = gU[sk][ty + 1][tx], gu1 = gU[sk][ty + 1][tx + 1];
+                const T gum = gU[sk][ty][tx], guz = gU[sp][ty + 1][tx];
+                const T gv0 = gV[sk][ty][tx + 1], gv1 = gV[sk][ty + 1][tx + 1];
+                const T gvm = gV[sk][ty][tx], gvz = gV[sp][ty][tx + 1];
+                const T gw0 = gW[sk][ty + 1][tx + 1], gw1 = gW[sn][ty + 1][tx + 1];
+                const T gwx = gW[sk][ty + 1][tx], gwy = gW[sk][ty][tx + 1];
+                const long long o = g.idx(io, jo, k);
+                const T c1 = Cc[0], c2 = Cc[1];
+                const T cross = T(0.5) * fmin(c1, c2);
+                T y[6];
+                y[0] = acur[0] * ((gu0 - gu1) + (gv0 - gv1) + (gw0 - gw1));
+                y[1] = acur[1] * ((gu1 - gu0) + (gw0 - gw1)) + c1 * vcur[1] + cross * vcur[2];
+                y[2] = acur[2] * ((gv1 - gv0) + (gw0 - gw1)) + c2 * vcur[2] + cross * vcur[1];
+                y[3] = acur[3] * ((gu0 - gum) + (gv0 - gvm)) + Cc[2] * vcur[3];
+                y[4] = acur[4] * ((gu0 - guz) + (gw0 - gwx)) + Cc[3] * vcur[4];
+                y[5] = acur[5] * ((gv0 - gvz) + (gw0 - gwy)) + Cc[4] * vcur[5];
+#pragma unroll
+                for (int s = 0; s < 6; ++s) {
+                    q_out[s * NP + o] = y[s];
+                    const double yd = y[s];
+                    pq_n += (double)vcur[s] * yd;
+                    qz_n += (double)zcur[s] * yd;
+                    qdq_n += (double)dcur[s] * yd * yd;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 6; ++s) {
+                vcur[s] = vnext[s];
+                acur[s] = anext[s];
+                zcur[s] = znext[s];
+                dcur[s] = dnext[s];
+            }
+#pragma unroll
+            for (int s = 0; s < 5; ++s) Cc[s] = Cn[s];
+        }
+    }
+    double vv[5] = {rz_n, pq_n, qz_n, qdq_n, rr_n};
+    block_partial<5, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
+}
+
 // x += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r over the active tiles
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict__ x,
@@ -661,6 +944,39 @@ int tile3d_anchors() { return TX * TY * KZ; }
 int apply3d_grid(int count, int word) { return resident_grid(count, word, false); }
 
 int dir3d_grid(int count, int word) { return resident_grid(count, word, true); }
+
+// Workgroups of the fused 3D iteration (FP32): its occupancy x compute units.
+int fused3d_grid(int count) {
+    static int cache[16] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int& c = cache[dev & 15];
+    if (c == 0) {
+        int nb = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused3d<float, false>, NT, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            ncu < 1)
+            ncu = 1;
+        c = nb * ncu;
+    }
+    return std::max(1, std::min(std::min(count, kMaxTileBlocks), c));
+}
+
+void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v,
+                    const float* dinv, const float* a, const float* c, const float* K,
+                    const RedArgs& ra, hipStream_t s) {
+    if (tl.count <= 0) return;
+    const dim3 gs(fused3d_grid(tl.count));
+    if (init)
+        hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(NT), 0, s, g, tl, v, dinv, a, c, K,
+                           ra);
+    else
+        hipLaunchKernelGGL((k_fused3d<float, false>), gs, dim3(NT), 0, s, g, tl, v, dinv, a, c, K,
+                           ra);
+}
 
 template <typename T>
 void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* r, const T* zsrc,

@@ -221,6 +221,38 @@ int run_chunks_fused(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     }
 }
 
+// 3D counterpart of run_chunks_fused (k_fused3d over the active tiles).
+int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
+    const Geo& g = ctx->g;
+    hipStream_t s = ctx->stream;
+    const int nb = fused3d_grid(ctx->tiles.count);
+    double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)kMaxTileBlocks + 32};
+    const FusedVecs fv{ctx->x32, {ctx->r32, ctx->z32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
+    const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
+    launch_fused3d(g, ctx->tiles, true, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32, r0, s);
+    int chunk = 8;
+    int kidx = 1;
+    for (;;) {
+        for (int k = 0; k < chunk; ++k, ++kidx) {
+            const RedArgs ra{ctx->sc, part[(kidx + 1) & 1], nb, part[kidx & 1], kidx,
+                             (set_bb && kidx == 1) ? 1 : 0};
+            if (ctx->prof && k == 1) HIPCHK(hipEventRecord(ctx->pev[0], s));
+            launch_fused3d(g, ctx->tiles, false, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32, ra,
+                           s);
+        }
+        if (ctx->prof) HIPCHK(hipEventRecord(ctx->pev[1], s));
+        HIPCHK(hipGetLastError());
+        int rc = read_scalars(ctx, 0, out);
+        if (rc) return rc;
+        if (ctx->prof && !out->done) {
+            ctx->prof_apply_ms += elapsed(ctx->pev[0], ctx->pev[1]) / (chunk - 1);
+            ++ctx->prof_apply_n;
+        }
+        if (out->done) return VFS_OK;
+        chunk = std::min(chunk * 2, 256);
+    }
+}
+
 // Truncated flexible CG (kFcgMax previous directions) with the learned
 // two-level preconditioner (3D, FP32): z = a1 D^-1 r + w network(r1) from the
 // (r.D^-1 r, r.r) partials of the previous kernel (net_precond), then the
@@ -304,10 +336,9 @@ int zero_dirs(vfs_ctx* ctx, bool f32) {
         HIPCHK(hipMemsetAsync(ctx->p032, 0, n * sizeof(float), ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->p132, 0, n * sizeof(float), ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->q32, 0, n * sizeof(float), ctx->stream));
-        if (ctx->g.dim == 2) {   // second r and q buffers of the fused 2D CG
-            HIPCHK(hipMemsetAsync(ctx->z32, 0, n * sizeof(float), ctx->stream));
-            HIPCHK(hipMemsetAsync(ctx->f32b, 0, n * sizeof(float), ctx->stream));
-        }
+        // second r and q buffers of the fused iteration
+        HIPCHK(hipMemsetAsync(ctx->z32, 0, n * sizeof(float), ctx->stream));
+        HIPCHK(hipMemsetAsync(ctx->f32b, 0, n * sizeof(float), ctx->stream));
     } else {
         HIPCHK(hipMemsetAsync(ctx->p0, 0, n * sizeof(double), ctx->stream));
         HIPCHK(hipMemsetAsync(ctx->p1, 0, n * sizeof(double), ctx->stream));
@@ -406,7 +437,7 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
         else if (g.dim == 2)
             rc = run_chunks_fused(ctx, true, &s);
         else
-            rc = run_chunks<float>(ctx, v, true, &s);
+            rc = run_chunks_fused3d(ctx, true, &s);
         if (rc) return rc;
         total += s.iter;
         fallbacks += s.fallbacks;
@@ -697,10 +728,9 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
     int ntx2 = 0, nty2 = 0;
     if (dim == 2) fused2d_tile_dims(g, ntx2, nty2);
     const long long nt2 = (long long)ntx2 * nty2;
-    if (dim == 2) {
-        ALLOC(ctx->f32b, ns * NP);
-        ALLOC(ctx->fpart, 10 * nt2 + 64);
-    }
+    // second r / q buffers and the two partial regions of the fused iteration
+    ALLOC(ctx->f32b, ns * NP);
+    ALLOC(ctx->fpart, 10 * (dim == 2 ? nt2 : (long long)kMaxTileBlocks) + 64);
     ctx->capA = apply_grid_blocks(g) + 16;
     ctx->capB = std::max(apply_grid_blocks(g), vec_grid_blocks(g)) + 16;
     ALLOC(ctx->partials, 2 * ctx->capA + 2 * ctx->capB + 64);

@@ -83,8 +83,8 @@ struct Scalars {
     double pqh[8];      // p.Ap of iteration k in slot k & 7 (truncated flexible CG)
 };
 
-// Vectors of the fused 2D CG (one launch per iteration): x in place; r, p
-// and q = A p double-buffered by launch parity.
+// Vectors of the fused CG iteration (one launch per iteration, 2D and 3D):
+// x in place; r, p and q = A p double-buffered by launch parity.
 struct FusedVecs {
     void* x;
     void* r[2];
@@ -282,6 +282,11 @@ int apply_blocks(const Geo& g, const Tiles& tl, int word);
 int dir_apply_blocks(const Geo& g, const Tiles& tl, int word);
 int apply3d_grid(int count, int word);
 int dir3d_grid(int count, int word);
+// one launch per Jacobi-PCG iteration in 3D (FP32), k_apply3d.hip
+int fused3d_grid(int count);
+void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v,
+                    const float* dinv, const float* a, const float* c, const float* K,
+                    const RedArgs& ra, hipStream_t s);
 // anchor positions of one tile of the 3D kernels and of the fused 2D kernel
 int tile3d_anchors();
 int tile2d_anchors();
