@@ -215,7 +215,8 @@ typedef struct vfs_batch vfs_batch;
 typedef struct vfs_batch_stats {
     int32_t n_problems;
     int32_t variant;          /* tile shape index (vfs_batch_variant_shape) */
-    int32_t blocks_per_cu;    /* persistent workgroups per compute unit */
+    int32_t blocks_per_cu;    /* persistent workgroups per compute unit (the requested
+                                 number, capped at what can be resident) */
     int32_t grid;             /* persistent workgroups launched */
     int32_t graph_used;       /* 1 if the pass ran from a hipGraph */
     int32_t status;           /* VFS_OK or VFS_ENOTCONV */
@@ -247,6 +248,10 @@ int vfs_batch_set_solver(vfs_batch* b, double rel_tol, int max_iter, double w_mi
 int vfs_batch_num_variants(void);
 int vfs_batch_variant_shape(int variant, int* bx, int* by);
 int vfs_batch_set_tiles(vfs_batch* b, int variant, int blocks_per_cu);
+/* Most persistent workgroups per compute unit that can be resident at once
+ * with the given tile shape on the current device (vfs_batch_set_tiles caps
+ * its request at this); < 0 for a bad variant or a failed query. */
+int vfs_batch_max_blocks_per_cu(int variant);
 /* Autotuner probe: device time per CG iteration of the persistent kernel
  * for a configuration, measured over `iterations` iterations on the
  * currently assembled problems (requires one vfs_batch_step before). */

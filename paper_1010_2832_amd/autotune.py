@@ -1,7 +1,8 @@
 """Autotuner for the batched persistent 2D solve.
 
 Sweeps every compiled tile shape (vfs_batch_variant_shape) and a range of
-persistent workgroups per compute unit, timing a fixed number of CG
+persistent workgroups per compute unit (capped at what can be resident,
+vfs_batch_max_blocks_per_cu), timing a fixed number of CG
 iterations of the persistent kernel on the batch's assembled problems
 (vfs_batch_time_variant), and applies the fastest.  Results are cached as
 JSON keyed by device name and the multiset of problem sizes, so a later
@@ -48,7 +49,9 @@ def tune(batch, iterations=40, blocks_per_cu=(1, 2, 4), cache_path=DEFAULT_CACHE
         return dict(best, cached=True)
     table = []
     for v in range(V.vfs_batch_num_variants()):
-        for bpc in blocks_per_cu:
+        # only counts that can all be resident (larger requests are capped)
+        cap = V.vfs_batch_max_blocks_per_cu(v)
+        for bpc in sorted({min(b, cap) for b in blocks_per_cu}):
             ms = batch.vfs_batch_time_variant(v, bpc, iterations)
             table.append(dict(variant=v, shape=V.vfs_batch_variant_shape(v), blocks_per_cu=bpc,
                               ms_per_iteration=ms))

@@ -6,8 +6,13 @@
 // contiguous chunks per workgroup.  One persistent kernel runs the whole
 // mixed-precision solve of every problem: FP32 Jacobi-PCG inner solves and
 // FP64 iterative refinement, as a per-problem state machine whose phases are
-// separated by a grid barrier.  A problem's reductions use the same
-// fence-free partials as the single-problem path (one partial per item,
+// separated by a grid barrier.  An inner CG iteration takes one phase: the
+// one-reduction form of the fused single-problem kernel (the update of the
+// previous iteration carried out lazily on each tile and its halo, the next
+// r.z from the expansion r.z - 2 alpha q.D^-1 r + alpha^2 q.D^-1 q), with r,
+// p and q double-buffered by iteration parity and the five partials of a
+// problem alternating between two regions.  A problem's reductions use the
+// same fence-free partials as the single-problem path (one partial per item,
 // summed in a fixed order by every item of that problem; a workgroup caches
 // the totals of the problem it is working on).  Each problem retires on its
 // own as soon as its FP64 residual meets the tolerance, stamping the device
@@ -121,15 +126,14 @@ __device__ __forceinline__ void item_partial(double (&v)[NV], double* __restrict
     __syncthreads();
 }
 
-// One 2D tile of the fused apply on problem pb (same arithmetic as the
-// single-problem kernel).  MODE 0: direction p = z + beta p_in, q = A p,
-// returns this thread's share of p.q.  MODE 2: r = b - A x (FP64), returns r.r.
-template <typename T, int BX, int BY, int MODE>
-__device__ double tile_apply(const Geo& g, int i0, int j0, const T* __restrict__ r,
-                             const T* __restrict__ dinv, const T* __restrict__ pin,
-                             T* __restrict__ pout, T* __restrict__ q, const T* __restrict__ a,
-                             const T* __restrict__ c, const T* __restrict__ K,
-                             const T* __restrict__ bv, T beta, bool first, T* lds) {
+// One 2D tile of the FP64 residual r = b - A x (the single-problem apply's
+// arithmetic); returns this thread's share of r.r.
+template <int BX, int BY>
+__device__ double tile_resid(const Geo& g, int i0, int j0, const double* __restrict__ xin,
+                             double* __restrict__ rout, const double* __restrict__ a,
+                             const double* __restrict__ c, const double* __restrict__ K,
+                             const double* __restrict__ bv, double* lds) {
+    using T = double;
     // lds layout: sW[3][BY+2][BX+2], sV[3][BY+2][BX+2], sG[2][BY+1][BX+1]
     constexpr int HX = BX + 2, HY = BY + 2, FX = BX + 1, FY = BY + 1;
     T* sW = lds;
@@ -144,20 +148,11 @@ __device__ double tile_apply(const Geo& g, int i0, int j0, const T* __restrict__
         T w[3] = {T(0), T(0), T(0)};
         if (i <= g.nx + 1 && j <= g.ny + 1) {
             const long long o = g.idx(i, j);
-            const bool own = li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 const long long os = o + s * NP;
-                T val;
-                if (MODE == 0) {
-                    const T z = dinv[os] * r[os];
-                    val = first ? z : z + beta * pin[os];
-                    if (own) pout[os] = val;
-                } else {
-                    val = pin[os];
-                }
-                v[s] = val;
-                w[s] = a[os] * val;
+                v[s] = xin[os];
+                w[s] = a[os] * v[s];
             }
         }
 #pragma unroll
@@ -203,27 +198,178 @@ __device__ double tile_apply(const Geo& g, int i0, int j0, const T* __restrict__
         const T gu0 = G_(0, ty + 1, tx), gu1 = G_(0, ty + 1, tx + 1), gum = G_(0, ty, tx);
         const T gv0 = G_(1, ty, tx + 1), gv1 = G_(1, ty + 1, tx + 1), gvm = G_(1, ty, tx);
 #undef G_
-        const T v0 = sV[(0 * HY + ty + 1) * HX + tx + 1];
         const T v1 = sV[(1 * HY + ty + 1) * HX + tx + 1];
         const T v2 = sV[(2 * HY + ty + 1) * HX + tx + 1];
         const T y0 = a[o] * ((gu0 - gu1) + (gv0 - gv1));
         const T y1 = a[NP + o] * ((gu1 - gu0) + (gv0 - gv1)) + c[NP + o] * v1;
         const T y2 = a[2 * NP + o] * ((gu0 - gum) + (gv0 - gvm)) + c[2 * NP + o] * v2;
-        if (MODE == 2) {
-            const T r0 = bv[o] - y0, r1 = bv[NP + o] - y1, r2 = bv[2 * NP + o] - y2;
-            q[o] = r0;
-            q[NP + o] = r1;
-            q[2 * NP + o] = r2;
-            acc += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
-        } else {
-            q[o] = y0;
-            q[NP + o] = y1;
-            q[2 * NP + o] = y2;
-            acc += (double)v0 * y0 + (double)v1 * y1 + (double)v2 * y2;
-        }
+        const T r0 = bv[o] - y0, r1 = bv[NP + o] - y1, r2 = bv[2 * NP + o] - y2;
+        rout[o] = r0;
+        rout[NP + o] = r1;
+        rout[2 * NP + o] = r2;
+        acc += r0 * r0 + r1 * r1 + r2 * r2;
     }
     __syncthreads();   // LDS reuse by the next tile
     return acc;
+}
+
+// One 2D tile of the fused CG iteration k on problem P (the arithmetic of the
+// single-problem fused kernel).  INIT (k = 0): z = D^-1 r, p = z, q = A p.
+// Otherwise r = r_{k-1} - alpha q_{k-1} on the tile and its halo, x += alpha
+// p_{k-1} at the own anchors, z = D^-1 r, p = z + beta p_{k-1}, q = A p.
+// Adds this thread's shares of (r.z, p.q, q.z, q.D^-1 q, r.r) to v.
+template <int BX, int BY, bool INIT>
+__device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float beta, int k,
+                           float* lds, double (&v)[5]) {
+    constexpr int HX = BX + 2, HY = BY + 2, FX = BX + 1, FY = BY + 1;
+    constexpr int RPT = BY * BX / NT;
+    constexpr int NE1 = (HX * HY + NT - 1) / NT;
+    constexpr int NE2 = (FX * FY + NT - 1) / NT;
+    static_assert(RPT * NT == BX * BY && NT % BX == 0, "tile must be a multiple of the workgroup");
+    const Geo& g = P.g;
+    const int pin = (k + 1) & 1, pout = k & 1;
+    float* const rv[2] = {P.r32, P.r32b};
+    float* const pv[2] = {P.p0, P.p1};
+    float* const qv[2] = {P.q32, P.q32b};
+    const float* __restrict__ r_in = rv[INIT ? 0 : pin];
+    const float* __restrict__ q_in = qv[pin];
+    const float* __restrict__ p_in = pv[pin];
+    float* __restrict__ r_out = rv[pout];
+    float* __restrict__ p_out = pv[pout];
+    float* __restrict__ q_out = qv[pout];
+    float* __restrict__ x = P.x32;
+    const float* __restrict__ dinv = P.dinv;
+    const float* __restrict__ a = P.a;
+    const float* __restrict__ c = P.c;
+    const float* __restrict__ K = P.K;
+    float* sV = lds;                     // p        [3][HY][HX]
+    float* sW = sV + 3 * HY * HX;        // a p
+    float* sZ = sW + 3 * HY * HX;        // z
+    float* sD = sZ + 3 * HY * HX;        // D^-1
+    float* sG = sD + 3 * HY * HX;        // faces    [2][FY][FX]
+    const long long NP = g.NP;
+    const int tid = threadIdx.x;
+#define L3(arr, s_, y_, x_) arr[((s_) * HY + (y_)) * HX + (x_)]
+#define G2(f_, y_, x_) sG[((f_) * FY + (y_)) * FX + (x_)]
+    float Rr[NE1][3], Dd[NE1][3], Qq[NE1][3], Pp[NE1][3], Aa[NE1][3], Xx[NE1][3];
+    bool in1[NE1], own1[NE1];
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+        const int e = tid + m * NT;
+        const int li = e % HX, lj = e / HX;
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        in1[m] = e < HX * HY && i <= g.nx + 1 && j <= g.ny + 1;
+        own1[m] = in1[m] && li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
+        const long long o = in1[m] ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const long long os = o + s * NP;
+            Rr[m][s] = Dd[m][s] = Qq[m][s] = Pp[m][s] = Aa[m][s] = Xx[m][s] = 0.f;
+            if (in1[m]) {
+                Rr[m][s] = r_in[os];
+                Dd[m][s] = dinv[os];
+                Aa[m][s] = a[os];
+                if (!INIT) {
+                    Qq[m][s] = q_in[os];
+                    Pp[m][s] = p_in[os];
+                }
+            }
+            if (!INIT && own1[m]) Xx[m][s] = x[os];
+        }
+    }
+    float Ku[NE2], Kv[NE2];
+#pragma unroll
+    for (int m = 0; m < NE2; ++m) {
+        const int e = tid + m * NT;
+        const int li = e % FX, lj = e / FX;
+        Ku[m] = Kv[m] = 0.f;
+        if (e < FX * FY) {
+            const int iu = i0 + li, ju = j0 - 1 + lj;
+            if (iu <= g.nx && ju >= 0 && ju < g.ny) Ku[m] = K[g.idx(iu, ju)];
+            const int iv = i0 - 1 + li, jv = j0 + lj;
+            if (iv >= 0 && iv < g.nx && jv <= g.ny) Kv[m] = K[NP + g.idx(iv, jv)];
+        }
+    }
+    const int tx = tid % BX;
+    float Ao[RPT][3], Co[RPT][2];
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = tid / BX + rr * (NT / BX);
+        const int i = i0 + tx, j = j0 + ty;
+        const bool ok = i <= g.nx && j <= g.ny;
+        const long long o = ok ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) Ao[rr][s] = ok ? a[o + s * NP] : 0.f;
+        Co[rr][0] = ok ? c[NP + o] : 0.f;
+        Co[rr][1] = ok ? c[2 * NP + o] : 0.f;
+    }
+#pragma unroll
+    for (int m = 0; m < NE1; ++m) {
+        const int e = tid + m * NT;
+        if (e >= HX * HY) continue;
+        const int li = e % HX, lj = e / HX;
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        const long long o = in1[m] ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const float rn = INIT ? Rr[m][s] : Rr[m][s] - alpha * Qq[m][s];
+            const float zn = Dd[m][s] * rn;
+            const float pn = INIT ? zn : zn + beta * Pp[m][s];
+            if (own1[m]) {
+                const long long os = o + s * NP;
+                if (!INIT) {
+                    r_out[os] = rn;
+                    x[os] = Xx[m][s] + alpha * Pp[m][s];
+                }
+                p_out[os] = pn;
+                v[0] += (double)rn * (double)zn;
+                v[4] += (double)rn * (double)rn;
+            }
+            L3(sV, s, lj, li) = pn;
+            L3(sW, s, lj, li) = Aa[m][s] * pn;
+            L3(sZ, s, lj, li) = zn;
+            L3(sD, s, lj, li) = Dd[m][s];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NE2; ++m) {
+        const int e = tid + m * NT;
+        if (e >= FX * FY) continue;
+        const int li = e % FX, lj = e / FX;
+        G2(0, lj, li) = Ku[m] * ((L3(sW, 0, lj, li + 1) - L3(sW, 0, lj, li)) +
+                                 (L3(sW, 1, lj, li) - L3(sW, 1, lj, li + 1)) +
+                                 (L3(sW, 2, lj, li + 1) - L3(sW, 2, lj + 1, li + 1)));
+        G2(1, lj, li) = Kv[m] * ((L3(sW, 0, lj + 1, li) - L3(sW, 0, lj, li)) +
+                                 (L3(sW, 1, lj + 1, li) - L3(sW, 1, lj, li)) +
+                                 (L3(sW, 2, lj + 1, li) - L3(sW, 2, lj + 1, li + 1)));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = tid / BX + rr * (NT / BX);
+        const int i = i0 + tx, j = j0 + ty;
+        if (i <= g.nx && j <= g.ny) {
+            const long long o = g.idx(i, j);
+            const float gu0 = G2(0, ty + 1, tx), gu1 = G2(0, ty + 1, tx + 1), gum = G2(0, ty, tx);
+            const float gv0 = G2(1, ty, tx + 1), gv1 = G2(1, ty + 1, tx + 1), gvm = G2(1, ty, tx);
+            float y[3];
+            y[0] = Ao[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
+            y[1] = Ao[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * L3(sV, 1, ty + 1, tx + 1);
+            y[2] = Ao[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * L3(sV, 2, ty + 1, tx + 1);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                q_out[o + s * NP] = y[s];
+                const double yd = y[s];
+                v[1] += (double)L3(sV, s, ty + 1, tx + 1) * yd;
+                v[2] += (double)L3(sZ, s, ty + 1, tx + 1) * yd;
+                v[3] += (double)L3(sD, s, ty + 1, tx + 1) * yd * yd;
+            }
+        }
+    }
+#undef L3
+#undef G2
+    __syncthreads();   // LDS reuse by the next tile
 }
 
 __device__ __forceinline__ void item_of(const BatchArgs& A, int w, int& p, int& i0, int& j0,
@@ -246,9 +392,7 @@ __global__ __launch_bounds__(NT) void k_batch_resid(BatchArgs A) {
         const BProb& P = A.prob[p];
         double acc = 0.0;
         if (A.state[p].needs || A.first_pass)
-            acc = tile_apply<double, BX, BY, 2>(P.g, i0, j0, nullptr, nullptr, P.x64, nullptr,
-                                                P.r64, P.a64, P.c64, P.K64, P.b64, 0.0, true,
-                                                lds64);
+            acc = tile_resid<BX, BY>(P.g, i0, j0, P.x64, P.r64, P.a64, P.c64, P.K64, P.b64, lds64);
         double v[1] = {acc};
         item_partial<1>(v, A.partR, w);
     }
@@ -314,16 +458,18 @@ __global__ void k_batch_reset_ctl(BatchCtl* ctl) {
     }
 }
 
-// The persistent solve of every problem, refinement included.  Global
-// phases alternate A (even) and B (odd), separated by grid barriers.  Per
-// problem, by mode:
-//   CG      A: r.z / r.r totals, stop test, direction + FP32 apply, p.q partial
-//           B: p.q total, alpha, FP32 update, r.z / r.r partials
-//   stop -> AXPY (B: x64 += |r64| x32) -> RESID (A: r64 = b - A64 x64, FP64,
-//           |r64|^2 partial) -> DECIDE (B: |r64| total; DONE if it meets tol,
-//           else r32 = r64/|r64|, x32 = 0, r.z / r.r partials, back to CG).
-// Problems therefore retire independently; their completion time is the
-// device wall clock at DONE.
+// The persistent solve of every problem, refinement included.  One phase per
+// step, a grid barrier after each.  Per problem, by mode:
+//   CG      kloc 0: r32 given, z = D^-1 r, p = z, q = A p, five partials;
+//           kloc k >= 1: totals of iteration k-1 -> stop test, alpha_{k-1},
+//           beta_k; lazy update, direction, q = A p, five partials
+//   stop -> AXPY (x64 += |r64| x32) -> RESID (r64 = b - A64 x64, FP64,
+//           |r64|^2 partial) -> DECIDE (|r64| total; DONE if it meets tol,
+//           else r32 = r64/|r64|, x32 = 0 and back to CG at kloc 0).
+// DECIDE acts only in odd phases, so the count of retired problems changes
+// only there and every workgroup reads the same value of it in the even
+// phases, where the loop may end.  Problems therefore retire independently;
+// their completion time is the device wall clock at DONE.
 template <int BX, int BY>
 __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     extern __shared__ double lds_dyn[];
@@ -334,8 +480,8 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     const int per = (A.nitems + G - 1) / G;
     const int w0 = min(A.nitems, (int)blockIdx.x * per), w1 = min(A.nitems, w0 + per);
 
-    // initialise the r32 of problems that need a solve (first inner solve)
-    auto init_inner = [&](const BProb& P, int i0, int j0, double rho2, double (&v)[2]) {
+    // r32 = r64 / |r64|, x32 = 0 on the tile (start of an inner solve)
+    auto init_inner = [&](const BProb& P, int i0, int j0, double rho2) {
         const double inv = rho2 > 0.0 ? 1.0 / sqrt(rho2) : 0.0;
         for (int e = threadIdx.x; e < BX * BY; e += NT) {
             const int i = i0 + e % BX, j = j0 + e / BX;
@@ -344,12 +490,8 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 const long long os = o + s * P.g.NP;
-                const float ri = (float)(P.r64[os] * inv);
-                const float zi = P.dinv[os] * ri;
-                P.r32[os] = ri;
+                P.r32[os] = (float)(P.r64[os] * inv);
                 P.x32[os] = 0.f;
-                v[0] += (double)ri * (double)zi;
-                v[1] += (double)ri * (double)ri;
             }
         }
     };
@@ -360,167 +502,118 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
         item_of(A, w, p, i0, j0, BX, BY);
         const BProb& P = A.prob[p];
         BState& S = A.state[p];
-        double v[2] = {0.0, 0.0};
-        if (S.needs) init_inner(P, i0, j0, S.rho2, v);
+        if (S.needs) init_inner(P, i0, j0, S.rho2);
         if (w == P.item0 && threadIdx.x == 0) {
             S.ph[0].mode = S.needs ? BM_CG : BM_DONE;
             S.ph[0].kloc = 0;
             if (S.needs)
                 __hip_atomic_fetch_add(&ctl->n_need, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        item_partial<2>(v, A.partB, w);
     }
     if (!grid_barrier(ctl, G)) return;
     const int n_need = __hip_atomic_load(&ctl->n_need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (n_need == 0) return;
 
-    for (int phi = 0;; phi += 2) {
-        // ------------------------------------------------------------ phase A
-        {
-            const int cs = phi & 1, ns = cs ^ 1;
-            int cached = -1;
-            double rzk = 0.0, rrk = 0.0;
-            for (int w = w0; w < w1; ++w) {
-                int p, i0, j0;
-                item_of(A, w, p, i0, j0, BX, BY);
-                const BProb& P = A.prob[p];
-                BState& S = A.state[p];
-                const BPhase cur = S.ph[cs];
-                const bool owner = w == P.item0 && threadIdx.x == 0;
-                BPhase nxt = cur;
-                if (cur.mode == BM_CG) {
-                    const int k = cur.kloc;
+    for (int phi = 0;; ++phi) {
+        const int cs = phi & 1, ns = cs ^ 1;
+        const bool retire_phase = (phi & 1) != 0;
+        int cached = -1;
+        double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int w = w0; w < w1; ++w) {
+            int p, i0, j0;
+            item_of(A, w, p, i0, j0, BX, BY);
+            const BProb& P = A.prob[p];
+            BState& S = A.state[p];
+            const BPhase cur = S.ph[cs];
+            const bool owner = w == P.item0 && threadIdx.x == 0;
+            BPhase nxt = cur;
+            if (cur.mode == BM_CG) {
+                const int k = cur.kloc;
+                double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                if (k == 0) {
+                    tile_fused<BX, BY, true>(P, i0, j0, 0.f, 0.f, 0, lds32, v);
+                    item_partial<5>(v, A.partF[0], w);
+                    nxt.kloc = 1;
+                } else {
                     if (p != cached) {
-                        double tot[2];
-                        problem_total<2>(A.partB, P.item0, P.nt, tot);
-                        rzk = tot[0];
-                        rrk = tot[1];
+                        problem_total<5>(A.partF[(k + 1) & 1], P.item0, P.nt, tot);
                         cached = p;
                     }
-                    const double bb = k == 0 ? rrk : S.bb;
-                    const bool stop = !isfinite(rzk) || !isfinite(rrk) || rrk <= S.tol_in2 * bb ||
-                                      k >= A.max_iter_pass || S.iters_total + k >= A.max_iter;
-                    const double beta = k == 0 ? 0.0 : rzk / S.rz[(k + 1) & 1];
-                    double v[1] = {0.0};
-                    if (!stop) {
-                        float* pin = (k & 1) ? P.p1 : P.p0;
-                        float* pout = (k & 1) ? P.p0 : P.p1;
-                        v[0] = tile_apply<float, BX, BY, 0>(P.g, i0, j0, P.r32, P.dinv, pin, pout,
-                                                            P.q32, P.a, P.c, P.K, nullptr,
-                                                            (float)beta, k == 0, lds32);
-                    }
-                    item_partial<1>(v, A.partA, w);
-                    if (owner) {
-                        S.rz[k & 1] = rzk;
-                        if (k == 0) S.bb = bb;
-                        if (stop) {
-                            S.last_iter = k;
+                    const double rz = tot[0], pq = tot[1], qdr = tot[2], qdq = tot[3], rrk = tot[4];
+                    const double bb = k == 1 ? rrk : S.bb;
+                    const bool stop = !isfinite(rz) || !isfinite(rrk) || !isfinite(pq) ||
+                                      rrk <= S.tol_in2 * bb || k - 1 >= A.max_iter_pass ||
+                                      S.iters_total + k - 1 >= A.max_iter || !(pq > 0.0);
+                    if (stop) {
+                        if (owner) {
+                            S.last_iter = k - 1;
                             nxt.mode = BM_AXPY;
                         }
-                    }
-                } else if (cur.mode == BM_RESID) {
-                    double v[1];
-                    v[0] = tile_apply<double, BX, BY, 2>(P.g, i0, j0, nullptr, nullptr, P.x64,
-                                                         nullptr, P.r64, P.a64, P.c64, P.K64,
-                                                         P.b64, 0.0, true, lds64);
-                    item_partial<1>(v, A.partR, w);
-                    nxt.mode = BM_DECIDE;
-                }
-                if (owner) S.ph[ns] = nxt;
-            }
-        }
-        // stops are counted only in phase B, so n_done is stable during phase A
-        const int nd = __hip_atomic_load(&ctl->n_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!grid_barrier(ctl, G)) return;
-        if (nd >= n_need) break;
-        // ------------------------------------------------------------ phase B
-        {
-            const int cs = (phi + 1) & 1, ns = cs ^ 1;
-            int cached = -1;
-            double pq = 0.0;
-            for (int w = w0; w < w1; ++w) {
-                int p, i0, j0;
-                item_of(A, w, p, i0, j0, BX, BY);
-                const BProb& P = A.prob[p];
-                BState& S = A.state[p];
-                const BPhase cur = S.ph[cs];
-                const bool owner = w == P.item0 && threadIdx.x == 0;
-                BPhase nxt = cur;
-                if (cur.mode == BM_CG) {
-                    const int k = cur.kloc;
-                    if (p != cached) {
-                        double tot[1];
-                        problem_total<1>(A.partA, P.item0, P.nt, tot);
-                        pq = tot[0];
-                        cached = p;
-                    }
-                    const float alpha = (pq > 0.0 && isfinite(pq)) ? (float)(S.rz[k & 1] / pq) : 0.f;
-                    const float* pk = (k & 1) ? P.p0 : P.p1;
-                    double v[2] = {0.0, 0.0};
-                    for (int e = threadIdx.x; e < BX * BY; e += NT) {
-                        const int i = i0 + e % BX, j = j0 + e / BX;
-                        if (i > P.g.nx || j > P.g.ny) continue;
-                        const long long o = P.g.idx(i, j);
-#pragma unroll
-                        for (int s = 0; s < 3; ++s) {
-                            const long long os = o + s * P.g.NP;
-                            const float ri = P.r32[os] - alpha * P.q32[os];
-                            const float zi = P.dinv[os] * ri;
-                            P.x32[os] = P.x32[os] + alpha * pk[os];
-                            P.r32[os] = ri;
-                            v[0] += (double)ri * (double)zi;
-                            v[1] += (double)ri * (double)ri;
-                        }
-                    }
-                    item_partial<2>(v, A.partB, w);
-                    nxt.kloc = k + 1;
-                } else if (cur.mode == BM_AXPY) {
-                    const double rho = sqrt(S.rho2);
-                    for (int e = threadIdx.x; e < BX * BY; e += NT) {
-                        const int i = i0 + e % BX, j = j0 + e / BX;
-                        if (i > P.g.nx || j > P.g.ny) continue;
-                        const long long o = P.g.idx(i, j);
-#pragma unroll
-                        for (int s = 0; s < 3; ++s)
-                            P.x64[o + s * P.g.NP] += rho * (double)P.x32[o + s * P.g.NP];
-                    }
-                    if (owner) {
-                        S.iters_total += S.last_iter;
-                        S.passes += 1;
-                    }
-                    nxt.mode = BM_RESID;
-                } else if (cur.mode == BM_DECIDE) {
-                    double tot[1];
-                    problem_total<1>(A.partR, P.item0, P.nt, tot);
-                    const double rho2 = tot[0];
-                    const double rel = S.bb64 > 0.0 ? sqrt(rho2 / S.bb64) : 0.0;
-                    const bool fin = !(rel > A.tol) || !isfinite(rel) || S.passes >= A.max_passes ||
-                                     S.iters_total >= A.max_iter;
-                    double v[2] = {0.0, 0.0};
-                    if (!fin) init_inner(P, i0, j0, rho2, v);
-                    item_partial<2>(v, A.partB, w);
-                    if (owner) {
-                        S.rho2 = rho2;
-                        S.rel = rel;
-                        if (fin) {
-                            nxt.mode = BM_DONE;
-                            S.t_done = wall_clock64();
-                            S.needs = 0;
-                            __hip_atomic_fetch_add(&ctl->n_done, 1, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-                        } else {
-                            double ti = rel > 0.0 ? 0.5 * A.tol / rel : 0.5;
-                            ti = ti < 1e-5 ? 1e-5 : (ti > 0.5 ? 0.5 : ti);
-                            S.tol_in2 = ti * ti;
-                            nxt.mode = BM_CG;
-                            nxt.kloc = 0;
-                        }
+                    } else {
+                        const double ad = rz / pq;
+                        const double rzn = rz - 2.0 * ad * qdr + ad * ad * qdq;
+                        const double bd = rz > 0.0 ? rzn / rz : 0.0;
+                        tile_fused<BX, BY, false>(P, i0, j0, (float)ad, (float)bd, k, lds32, v);
+                        item_partial<5>(v, A.partF[k & 1], w);
+                        if (owner && k == 1) S.bb = bb;
+                        nxt.kloc = k + 1;
                     }
                 }
-                if (owner) S.ph[ns] = nxt;
+            } else if (cur.mode == BM_AXPY) {
+                const double rho = sqrt(S.rho2);
+                for (int e = threadIdx.x; e < BX * BY; e += NT) {
+                    const int i = i0 + e % BX, j = j0 + e / BX;
+                    if (i > P.g.nx || j > P.g.ny) continue;
+                    const long long o = P.g.idx(i, j);
+#pragma unroll
+                    for (int s = 0; s < 3; ++s)
+                        P.x64[o + s * P.g.NP] += rho * (double)P.x32[o + s * P.g.NP];
+                }
+                if (owner) {
+                    S.iters_total += S.last_iter;
+                    S.passes += 1;
+                }
+                nxt.mode = BM_RESID;
+            } else if (cur.mode == BM_RESID) {
+                double v[1];
+                v[0] = tile_resid<BX, BY>(P.g, i0, j0, P.x64, P.r64, P.a64, P.c64, P.K64, P.b64,
+                                          lds64);
+                item_partial<1>(v, A.partR, w);
+                nxt.mode = BM_DECIDE;
+            } else if (cur.mode == BM_DECIDE && retire_phase) {
+                double t1[1];
+                problem_total<1>(A.partR, P.item0, P.nt, t1);
+                const double rho2 = t1[0];
+                const double rel = S.bb64 > 0.0 ? sqrt(rho2 / S.bb64) : 0.0;
+                const bool fin = !(rel > A.tol) || !isfinite(rel) || S.passes >= A.max_passes ||
+                                 S.iters_total >= A.max_iter;
+                if (!fin) init_inner(P, i0, j0, rho2);
+                if (owner) {
+                    S.rho2 = rho2;
+                    S.rel = rel;
+                    if (fin) {
+                        nxt.mode = BM_DONE;
+                        S.t_done = wall_clock64();
+                        S.needs = 0;
+                        __hip_atomic_fetch_add(&ctl->n_done, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        double ti = rel > 0.0 ? 0.5 * A.tol / rel : 0.5;
+                        ti = ti < 1e-5 ? 1e-5 : (ti > 0.5 ? 0.5 : ti);
+                        S.tol_in2 = ti * ti;
+                        nxt.mode = BM_CG;
+                        nxt.kloc = 0;
+                    }
+                }
             }
+            if (owner) S.ph[ns] = nxt;
         }
+        // retirements happen only in odd phases: the count is stable in even ones
+        const int nd = retire_phase ? 0
+                                    : __hip_atomic_load(&ctl->n_done, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
         if (!grid_barrier(ctl, G)) return;
+        if (!retire_phase && nd >= n_need) break;
     }
 }
 

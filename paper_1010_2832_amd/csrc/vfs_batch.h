@@ -13,6 +13,7 @@ struct BProb {
     Geo g;
     int item0, nt, ntx, nty;      // first work item, tiles (items) of this problem
     float *x32, *r32, *p0, *p1, *q32;
+    float *r32b, *q32b;           // second r and q buffers (iteration parity)
     const float *a, *c, *K, *dinv;
     double *x64, *r64;
     const double *a64, *c64, *K64, *b64;
@@ -32,7 +33,6 @@ struct BPhase {
 // read it).
 struct BState {
     BPhase ph[2];
-    double rz[2];
     double bb;        // |r32|^2 at the start of the pass (1 up to rounding)
     double rho2;      // |r64|^2 of the current iterate
     double bb64;      // |b|^2
@@ -61,7 +61,8 @@ struct BatchArgs {
     BatchCtl* ctl;
     const int* item_prob;
     int nitems, nprob;
-    double *partA, *partB, *partR;
+    double* partF[2];   // five CG partials per item, by iteration parity
+    double* partR;      // FP64 |r64|^2 partial per item
     double tol;
     int max_iter, max_iter_pass, max_passes;
     int first_pass;

@@ -26,7 +26,8 @@ struct vfs_batch {
     int max_passes = 8;
     // launch configuration (autotuned)
     int variant = 1;
-    int blocks_per_cu = 2;
+    int blocks_per_cu = 2;   // requested
+    int bpc_used = 0;        // after the occupancy limit
     int grid = 0;
     int ncu = 0;
     // device structures
@@ -76,9 +77,9 @@ BatchArgs args(vfs_batch* b, int first_pass) {
     A.item_prob = b->d_item_prob;
     A.nitems = b->nitems;
     A.nprob = b->n;
-    A.partA = b->d_part;
-    A.partB = b->d_part + b->part_cap;
-    A.partR = b->d_part + 3 * b->part_cap;
+    A.partF[0] = b->d_part;
+    A.partF[1] = b->d_part + 5 * b->part_cap;
+    A.partR = b->d_part + 10 * b->part_cap;
     A.tol = b->tol;
     A.max_iter = b->max_iter;
     A.max_iter_pass = b->max_iter_pass;
@@ -108,6 +109,8 @@ int build_items(vfs_batch* b) {
         P.p0 = c->p032;
         P.p1 = c->p132;
         P.q32 = c->q32;
+        P.r32b = c->z32;
+        P.q32b = c->f32b;
         P.a = c->a32;
         P.c = c->c32;
         P.K = c->K32;
@@ -125,8 +128,8 @@ int build_items(vfs_batch* b) {
     b->d_item_prob = nullptr;
     b->d_part = nullptr;
     BCHK(hipMalloc((void**)&b->d_item_prob, sizeof(int) * b->nitems));
-    b->part_cap = 2LL * b->nitems + 64;
-    BCHK(hipMalloc((void**)&b->d_part, sizeof(double) * 4 * b->part_cap));
+    b->part_cap = (long long)b->nitems + 64;
+    BCHK(hipMalloc((void**)&b->d_part, sizeof(double) * 11 * b->part_cap));
     BCHK(hipMemcpy(b->d_item_prob, item_prob.data(), sizeof(int) * b->nitems,
                    hipMemcpyHostToDevice));
     BCHK(hipMemcpy(b->d_prob, b->h_prob.data(), sizeof(BProb) * b->n, hipMemcpyHostToDevice));
@@ -134,6 +137,7 @@ int build_items(vfs_batch* b) {
     if (batch_pcg_occupancy(b->variant, &bpc) != 0 || bpc < 1)
         return bfail(b, VFS_EHIP, "occupancy query failed");
     const int use = std::max(1, std::min(b->blocks_per_cu, bpc));
+    b->bpc_used = use;
     b->grid = std::max(1, std::min(b->ncu * use, b->nitems));
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
@@ -379,7 +383,7 @@ int vfs_batch_step(vfs_batch* b, double dt) {
     S = vfs_batch_stats{};
     S.n_problems = b->n;
     S.variant = b->variant;
-    S.blocks_per_cu = b->blocks_per_cu;
+    S.blocks_per_cu = b->bpc_used;
     S.grid = b->grid;
     S.graph_used = b->graph_ok ? 1 : 0;
     S.status = status;
@@ -452,6 +456,13 @@ int vfs_batch_get_stats(vfs_batch* b, vfs_batch_stats* out) {
     if (!b || !out) return VFS_EINVAL;
     *out = b->stats;
     return VFS_OK;
+}
+
+int vfs_batch_max_blocks_per_cu(int variant) {
+    if (variant < 0 || variant >= kBatchVariants) return VFS_EINVAL;
+    int bpc = 0;
+    if (batch_pcg_occupancy(variant, &bpc) != 0 || bpc < 1) return VFS_EHIP;
+    return bpc;
 }
 
 int vfs_batch_time_variant(vfs_batch* b, int variant, int blocks_per_cu, int iterations,

@@ -114,6 +114,7 @@ _SIGS = {
     "vfs_batch_set_solver": ([_P, _D, _I, _D], _I),
     "vfs_batch_num_variants": ([], _I),
     "vfs_batch_variant_shape": ([_I, ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
+    "vfs_batch_max_blocks_per_cu": ([_I], _I),
     "vfs_batch_set_tiles": ([_P, _I, _I], _I),
     "vfs_batch_time_variant": ([_P, _I, _I, _I, ctypes.POINTER(_D)], _I),
     "vfs_batch_step": ([_P, _D], _I),
@@ -446,6 +447,13 @@ def vfs_batch_variant_shape(variant):
     bx, by = _I(), _I()
     _bcheck(None, _lib.vfs_batch_variant_shape(variant, ctypes.byref(bx), ctypes.byref(by)))
     return bx.value, by.value
+
+
+def vfs_batch_max_blocks_per_cu(variant):
+    rc = _lib.vfs_batch_max_blocks_per_cu(variant)
+    if rc < 0:
+        raise VfsError(rc, f"vfs_batch_max_blocks_per_cu({variant}) failed")
+    return rc
 
 
 class Batch:

@@ -77,10 +77,15 @@ def test_autotuner_picks_a_valid_configuration(tmp_path):
     _banner(f"  autotune {res['variant']} {res['blocks_per_cu']} {res['ms_per_iteration']:.4f} ms/iter")
     assert 0 <= res["variant"] < V.vfs_batch_num_variants()
     assert all(r["ms_per_iteration"] > 0 for r in res["table"])
+    # every timed configuration can be resident at once (the grid barrier needs it)
+    assert all(1 <= r["blocks_per_cu"] <= V.vfs_batch_max_blocks_per_cu(r["variant"])
+               for r in res["table"])
     again = autotune.tune(b, cache_path=str(tmp_path / "at.json"))
     assert again["cached"] and again["variant"] == res["variant"]
     b.vfs_batch_step(probs[0]["dt"])
-    assert b.vfs_batch_get_stats()["status"] == 0
+    st = b.vfs_batch_get_stats()
+    assert st["status"] == 0
+    assert st["blocks_per_cu"] == res["blocks_per_cu"]
     b.close()
 
 
