@@ -2,8 +2,8 @@
 // persistent launch.
 //
 // Every problem has its own padded arrays (assembled by the single-problem
-// kernels).  Work items are (problem, 2D tile) pairs, statically split into
-// contiguous chunks per workgroup.  One persistent kernel runs the whole
+// kernels).  Work items are (problem, 2D tile) pairs, dealt round-robin over
+// the workgroups.  One persistent kernel runs the whole
 // mixed-precision solve of every problem: FP32 Jacobi-PCG inner solves and
 // FP64 iterative refinement, as a per-problem state machine whose phases are
 // separated by a grid barrier.  An inner CG iteration takes one phase: the
@@ -477,8 +477,10 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     double* lds64 = lds_dyn;
     BatchCtl* ctl = A.ctl;
     const unsigned G = gridDim.x;
-    const int per = (A.nitems + G - 1) / G;
-    const int w0 = min(A.nitems, (int)blockIdx.x * per), w1 = min(A.nitems, w0 + per);
+    // items are dealt round-robin (item w to workgroup w mod G), so every
+    // problem's tiles are spread over the whole grid and the problems still
+    // iterating near the end of a solve keep every workgroup busy
+    const int wb = (int)blockIdx.x, ws = (int)G;
 
     // r32 = r64 / |r64|, x32 = 0 on the tile (start of an inner solve)
     auto init_inner = [&](const BProb& P, int i0, int j0, double rho2) {
@@ -497,7 +499,7 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     };
 
     // phase "-1": initial modes
-    for (int w = w0; w < w1; ++w) {
+    for (int w = wb; w < A.nitems; w += ws) {
         int p, i0, j0;
         item_of(A, w, p, i0, j0, BX, BY);
         const BProb& P = A.prob[p];
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
         const bool retire_phase = (phi & 1) != 0;
         int cached = -1;
         double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int w = w0; w < w1; ++w) {
+        for (int w = wb; w < A.nitems; w += ws) {
             int p, i0, j0;
             item_of(A, w, p, i0, j0, BX, BY);
             const BProb& P = A.prob[p];
