@@ -98,6 +98,34 @@ def cpu_baseline(case, iters, seconds_cap=30.0):
 WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96.npy")
 
 
+def config3_leg(V):
+    """FP64 plain PCG against mixed PCG with iterative refinement on the 3D
+    128^3 column configuration, both to a 1e-6 FP64 relative residual."""
+    import numpy as np
+    import cases
+    case = cases.config3()
+    out = {"workload": "3D 128^3 column (radius 0.05, top 0.8) on a solid floor, mu 50, rho 1, "
+                       "u = (0,-0.5,0), g (0,-9.8,0), dt 1e-3, seed 3, both to 1e-6"}
+    vel = {}
+    for name, prec in (("fp64", V.VFS_FP64), ("mixed", V.VFS_MIXED)):
+        ctx = V.context_from_case(case, precision=prec, tol=1e-6)
+        ctx.vfs_set_profiling(True)
+        ctx.vfs_step(case["dt"])   # first step: warms the code paths up
+        ctx.vfs_set_velocity(case["u"])
+        ctx.vfs_step(case["dt"])
+        st = ctx.vfs_get_stats()
+        vel[name] = np.concatenate([np.ravel(q) for q in ctx.vfs_get_velocity()])
+        out[name] = {"iterations": st["iterations"], "outer_iterations": st["outer_iterations"],
+                     "solve_ms": st["t_solve_ms"], "step_ms": st["t_step_ms"],
+                     "rel_residual_fp64": st["rel_residual"], "n_active": st["n_active"],
+                     "dof_iter_per_s": st["n_active"] * st["iterations"] / (st["t_solve_ms"] * 1e-3),
+                     "ms_per_iteration": st["t_solve_ms"] / max(1, st["iterations"])}
+        ctx.close()
+    scale = max(float(np.abs(vel["fp64"]).max()), 1e-300)
+    out["velocity_rel_linf_mixed_vs_fp64"] = float(np.abs(vel["mixed"] - vel["fp64"]).max()) / scale
+    return out
+
+
 def config5_leg(V, learned_cap=400):
     """Learned vs plain PCG on the 3D 256^3 configuration: Jacobi PCG in mixed
     precision to 1e-6, then truncated flexible CG with the committed network
@@ -151,6 +179,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--cpu-iters", type=int, default=400)
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the 128^3 FP64-vs-mixed leg")
     ap.add_argument("--no-config5", action="store_true",
                     help="skip the 256^3 learned-vs-plain leg")
     args = ap.parse_args()
@@ -261,6 +291,8 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
     ctx.close()
+    if not args.no_config3:
+        out["config3_fp64_vs_mixed"] = config3_leg(V)
     if not args.no_config5:
         out["config5_learned_vs_plain"] = config5_leg(V)
     print(json.dumps(out), flush=True)

@@ -45,14 +45,18 @@ __device__ __forceinline__ TileRange tile_range(int count) {
     return TileRange{t0 + slot, nblk, t1};
 }
 
-__device__ __forceinline__ void tile_origin(const Tiles& t, int w, int& i0, int& j0, int& k0) {
-    const int id = t.list[w];
+// Anchors of work item u: x from i0, y from j0, planes [k0, kend).
+__device__ __forceinline__ void tile_origin(const Tiles& t, const Geo& g, int u, int& i0, int& j0,
+                                            int& k0, int& kend) {
+    const int id = t.list[u / t.split];
     const int tx = id % t.ntx;
     const int ty = (id / t.ntx) % t.nty;
     const int tz = id / (t.ntx * t.nty);
+    const int kz = KZ / t.split;
     i0 = tx * TX;
     j0 = ty * TY;
-    k0 = tz * KZ;
+    k0 = tz * KZ + (u % t.split) * kz;
+    kend = min(k0 + kz, g.nz + 1);
 }
 
 template <typename T, int MODE, bool ZIN>
@@ -136,11 +140,10 @@ __global__ __launch_bounds__(NT) void k_apply3d(Geo g, Tiles tl, const T* __rest
         ld.prev[i] = static_cast<const T*>(ra.fh.P[i]);
     }
     double acc = 0.0;
-  const TileRange tr = tile_range(tl.count);
+  const TileRange tr = tile_range(tl.items());
   for (int wtile = tr.first; wtile < tr.end; wtile += tr.step) {
-    int i0, j0, k0;
-    tile_origin(tl, wtile, i0, j0, k0);
-    const int kend = min(k0 + KZ, g.nz + 1);
+    int i0, j0, k0, kend;
+    tile_origin(tl, g, wtile, i0, j0, k0, kend);
     T vcur[6], acur[6], vnext[6], anext[6];
     __syncthreads();   // LDS of the previous tile is no longer read
     // load weighted plane kk into ring slot kk&1; own anchor values -> vo, ao
@@ -349,11 +352,10 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
     }
     constexpr int NF = (FX * FY + NT - 1) / NT;
     double acc = 0.0;
-    const TileRange trg = tile_range(tl.count);
+    const TileRange trg = tile_range(tl.items());
     for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
-        int i0, j0, k0;
-        tile_origin(tl, wtile, i0, j0, k0);
-        const int kend = min(k0 + KZ, g.nz + 1);
+        int i0, j0, k0, kend;
+        tile_origin(tl, g, wtile, i0, j0, k0, kend);
         const int io = i0 + tx, jo = j0 + ty;
         const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
 
@@ -610,11 +612,10 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
     }
     constexpr int NF = (FX * FY + NT - 1) / NT;
     double rz_n = 0.0, rr_n = 0.0, pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
-    const TileRange trg = tile_range(tl.count);
+    const TileRange trg = tile_range(tl.items());
     for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
-        int i0, j0, k0;
-        tile_origin(tl, wtile, i0, j0, k0);
-        const int kend = min(k0 + KZ, g.nz + 1);
+        int i0, j0, k0, kend;
+        tile_origin(tl, g, wtile, i0, j0, k0, kend);
         const int io = i0 + tx, jo = j0 + ty;
         const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
 
@@ -822,11 +823,10 @@ __global__ __launch_bounds__(NT) void k_update3d(Geo g, Tiles tl, T* __restrict_
     const T alpha = (T)alpha_d;
     const long long NP = g.NP;
     double rz = 0.0, rr = 0.0;
-    const TileRange tr = tile_range(tl.count);
+    const TileRange tr = tile_range(tl.items());
   for (int wtile = tr.first; wtile < tr.end; wtile += tr.step) {
-        int i0, j0, k0;
-        tile_origin(tl, wtile, i0, j0, k0);
-        const int kend = min(k0 + KZ, g.nz + 1);
+        int i0, j0, k0, kend;
+        tile_origin(tl, g, wtile, i0, j0, k0, kend);
         const int i = i0 + (threadIdx.x & 63), j = j0 + (threadIdx.x >> 6);
         if (!(i <= g.nx && j <= g.ny)) continue;
         for (int k = k0; k < kend; ++k) {
@@ -941,6 +941,23 @@ static int resident_grid(int count, int word, bool pipelined) {
 
 int tile3d_anchors() { return TX * TY * KZ; }
 
+// Plane split of a tile list of `count` tiles: the smallest power of two (at
+// most KZ) that gives at least two work items per compute unit, the
+// resident grid of the pipelined and fused kernels.
+int tile_split(int count) {
+    static int ncu_cache[16] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int& ncu = ncu_cache[dev & 15];
+    if (ncu == 0 &&
+        (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+         ncu < 1))
+        ncu = 1;
+    int split = 1;
+    while (split < KZ && (long long)count * split < 2LL * ncu) split *= 2;
+    return split;
+}
+
 int apply3d_grid(int count, int word) { return resident_grid(count, word, false); }
 
 int dir3d_grid(int count, int word) { return resident_grid(count, word, true); }
@@ -969,7 +986,7 @@ void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v
                     const float* dinv, const float* a, const float* c, const float* K,
                     const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    const dim3 gs(fused3d_grid(tl.count));
+    const dim3 gs(fused3d_grid(tl.items()));
     if (init)
         hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(NT), 0, s, g, tl, v, dinv, a, c, K,
                            ra);
@@ -983,13 +1000,13 @@ void launch_apply3d(const Geo& g, const Tiles& tl, int mode, bool zin, const T* 
                     const T* dinv, const T* pin, T* pout, T* q, const T* a, const T* c,
                     const T* K, const T* bvec, const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    const dim3 gs(apply3d_grid(tl.count, (int)sizeof(T)));
+    const dim3 gs(apply3d_grid(tl.items(), (int)sizeof(T)));
     if (mode == MODE_DIR) {
         if (zin)
             hipLaunchKernelGGL((k_apply3d<T, MODE_DIR, true>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
                                dinv, pin, pout, q, a, c, K, bvec, ra);
         else
-            hipLaunchKernelGGL((k_dir3d_pipe<T>), dim3(dir3d_grid(tl.count, (int)sizeof(T))),
+            hipLaunchKernelGGL((k_dir3d_pipe<T>), dim3(dir3d_grid(tl.items(), (int)sizeof(T))),
                                dim3(NT), 0, s, g, tl, r, dinv, pin, pout, q, a, c, K, ra);
     } else if (mode == MODE_FDIR) {
         hipLaunchKernelGGL((k_apply3d<T, MODE_FDIR, false>), gs, dim3(NT), 0, s, g, tl, r, zsrc,
@@ -1014,7 +1031,7 @@ template <typename T>
 void launch_update3d(const Geo& g, const Tiles& tl, T* x, const T* p, T* r, const T* q,
                      const T* dinv, T* z, const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    hipLaunchKernelGGL((k_update3d<T>), dim3(std::min(tl.count, kMaxTileBlocks)), dim3(NT), 0, s, g,
+    hipLaunchKernelGGL((k_update3d<T>), dim3(std::min(tl.items(), kMaxTileBlocks)), dim3(NT), 0, s, g,
                        tl, x, p, r, q, dinv, z, ra);
 }
 

@@ -387,15 +387,15 @@ int vec_grid_blocks(const Geo& g) {
 }
 
 int apply_blocks(const Geo& g, const Tiles& tl, int word) {
-    return g.dim == 2 ? apply_grid_blocks(g) : apply3d_grid(tl.count, word);
+    return g.dim == 2 ? apply_grid_blocks(g) : apply3d_grid(tl.items(), word);
 }
 
 int dir_apply_blocks(const Geo& g, const Tiles& tl, int word) {
-    return g.dim == 2 ? apply_grid_blocks(g) : dir3d_grid(tl.count, word);
+    return g.dim == 2 ? apply_grid_blocks(g) : dir3d_grid(tl.items(), word);
 }
 
 int update_blocks(const Geo& g, const Tiles& tl) {
-    return g.dim == 2 ? vec_grid_blocks(g) : std::min(tl.count, kMaxTileBlocks);
+    return g.dim == 2 ? vec_grid_blocks(g) : std::min(tl.items(), kMaxTileBlocks);
 }
 
 template <typename T>

@@ -225,7 +225,7 @@ int run_chunks_fused(vfs_ctx* ctx, bool set_bb, Scalars* out) {
 int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     const Geo& g = ctx->g;
     hipStream_t s = ctx->stream;
-    const int nb = fused3d_grid(ctx->tiles.count);
+    const int nb = fused3d_grid(ctx->tiles.items());
     double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)kMaxTileBlocks + 32};
     const FusedVecs fv{ctx->x32, {ctx->r32, ctx->z32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
     const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
@@ -521,6 +521,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         HIPCHK(hipStreamSynchronize(s));
         ctx->tiles.list = ctx->tile_list;
         ctx->tiles.count = *ctx->tile_count_host;
+        ctx->tiles.split = tile_split(ctx->tiles.count);
         ctx->stats.n_tile_samples = (int64_t)ctx->tiles.count * tile3d_anchors() * g.nsamp();
     }
     if (ctx->precision == VFS_MIXED) {
@@ -731,8 +732,10 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
     // second r / q buffers and the two partial regions of the fused iteration
     ALLOC(ctx->f32b, ns * NP);
     ALLOC(ctx->fpart, 10 * (dim == 2 ? nt2 : (long long)kMaxTileBlocks) + 64);
-    ctx->capA = apply_grid_blocks(g) + 16;
-    ctx->capB = std::max(apply_grid_blocks(g), vec_grid_blocks(g)) + 16;
+    // 3D grids are capped at kMaxTileBlocks workgroups, not at the tile count
+    const int maxA = std::max(apply_grid_blocks(g), dim == 3 ? kMaxTileBlocks : 0);
+    ctx->capA = maxA + 16;
+    ctx->capB = std::max(maxA, vec_grid_blocks(g)) + 16;
     ALLOC(ctx->partials, 2 * ctx->capA + 2 * ctx->capB + 64);
     ALLOC(ctx->counter, 16);
     ALLOC(ctx->sc, 4);

@@ -116,11 +116,16 @@ struct RedArgs {
 };
 
 // Compacted list of active 3D tiles (64 x 4 anchors in x,y times 8 planes
-// in z); unused in 2D.
+// in z); unused in 2D.  When the list is short the planes of each tile are
+// shared by `split` work items (1, 2, 4 or 8; item u covers tile u / split,
+// planes part (u % split) of it), so a small active set still spreads over
+// the whole chip and each workgroup marches fewer planes.
 struct Tiles {
     const int* list;
     int count;
     int ntx, nty, ntz;
+    int split = 1;
+    __host__ __device__ int items() const { return count * split; }
 };
 
 }  // namespace vfs
@@ -289,6 +294,8 @@ void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v
                     const RedArgs& ra, hipStream_t s);
 // anchor positions of one tile of the 3D kernels and of the fused 2D kernel
 int tile3d_anchors();
+// plane split of a 3D tile list (Tiles::split)
+int tile_split(int count);
 int tile2d_anchors();
 // fused 2D CG over the compacted list of tiles holding an active sample
 void fused2d_tile_dims(const Geo& g, int& ntx, int& nty);
