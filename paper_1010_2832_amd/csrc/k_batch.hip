@@ -508,6 +508,7 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
         if (w == P.item0 && threadIdx.x == 0) {
             S.ph[0].mode = S.needs ? BM_CG : BM_DONE;
             S.ph[0].kloc = 0;
+            S.retired = S.needs ? 0 : 1;
             if (S.needs)
                 __hip_atomic_fetch_add(&ctl->n_need, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -516,99 +517,123 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     const int n_need = __hip_atomic_load(&ctl->n_need, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (n_need == 0) return;
 
+    __shared__ int s_list[NT];
+    __shared__ int s_wcnt[NT / 64];
     for (int phi = 0;; ++phi) {
         const int cs = phi & 1, ns = cs ^ 1;
         const bool retire_phase = (phi & 1) != 0;
         int cached = -1;
         double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int w = wb; w < A.nitems; w += ws) {
-            int p, i0, j0;
-            item_of(A, w, p, i0, j0, BX, BY);
-            const BProb& P = A.prob[p];
-            BState& S = A.state[p];
-            const BPhase cur = S.ph[cs];
-            const bool owner = w == P.item0 && threadIdx.x == 0;
-            BPhase nxt = cur;
-            if (cur.mode == BM_CG) {
-                const int k = cur.kloc;
-                double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                if (k == 0) {
-                    tile_fused<BX, BY, true>(P, i0, j0, 0.f, 0.f, 0, lds32, v);
-                    item_partial<5>(v, A.partF[0], w);
-                    nxt.kloc = 1;
-                } else {
-                    if (p != cached) {
-                        problem_total<5>(A.partF[(k + 1) & 1], P.item0, P.nt, tot);
-                        cached = p;
-                    }
-                    const double rz = tot[0], pq = tot[1], qdr = tot[2], qdq = tot[3], rrk = tot[4];
-                    const double bb = k == 1 ? rrk : S.bb;
-                    const bool stop = !isfinite(rz) || !isfinite(rrk) || !isfinite(pq) ||
-                                      rrk <= S.tol_in2 * bb || k - 1 >= A.max_iter_pass ||
-                                      S.iters_total + k - 1 >= A.max_iter || !(pq > 0.0);
-                    if (stop) {
-                        if (owner) {
-                            S.last_iter = k - 1;
-                            nxt.mode = BM_AXPY;
-                        }
-                    } else {
-                        const double ad = rz / pq;
-                        const double rzn = rz - 2.0 * ad * qdr + ad * ad * qdq;
-                        const double bd = rz > 0.0 ? rzn / rz : 0.0;
-                        tile_fused<BX, BY, false>(P, i0, j0, (float)ad, (float)bd, k, lds32, v);
-                        item_partial<5>(v, A.partF[k & 1], w);
-                        if (owner && k == 1) S.bb = bb;
-                        nxt.kloc = k + 1;
-                    }
-                }
-            } else if (cur.mode == BM_AXPY) {
-                const double rho = sqrt(S.rho2);
-                for (int e = threadIdx.x; e < BX * BY; e += NT) {
-                    const int i = i0 + e % BX, j = j0 + e / BX;
-                    if (i > P.g.nx || j > P.g.ny) continue;
-                    const long long o = P.g.idx(i, j);
+        // gather this workgroup's items of problems that have not retired (up
+        // to NT per round, in item order): the mode reads of all items are in
+        // flight together instead of one dependent chain per item
+        for (int r0 = 0; wb + r0 * ws < A.nitems; r0 += NT) {
+            const int wt = wb + (r0 + (int)threadIdx.x) * ws;
+            const bool act = wt < A.nitems && !A.state[A.item_prob[wt]].retired;
+            const unsigned long long bal = __ballot(act);
+            const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+            if (lane == 0) s_wcnt[wid] = __popcll(bal);
+            __syncthreads();
+            int off = 0, nact = 0;
 #pragma unroll
-                    for (int s = 0; s < 3; ++s)
-                        P.x64[o + s * P.g.NP] += rho * (double)P.x32[o + s * P.g.NP];
-                }
-                if (owner) {
-                    S.iters_total += S.last_iter;
-                    S.passes += 1;
-                }
-                nxt.mode = BM_RESID;
-            } else if (cur.mode == BM_RESID) {
-                double v[1];
-                v[0] = tile_resid<BX, BY>(P.g, i0, j0, P.x64, P.r64, P.a64, P.c64, P.K64, P.b64,
-                                          lds64);
-                item_partial<1>(v, A.partR, w);
-                nxt.mode = BM_DECIDE;
-            } else if (cur.mode == BM_DECIDE && retire_phase) {
-                double t1[1];
-                problem_total<1>(A.partR, P.item0, P.nt, t1);
-                const double rho2 = t1[0];
-                const double rel = S.bb64 > 0.0 ? sqrt(rho2 / S.bb64) : 0.0;
-                const bool fin = !(rel > A.tol) || !isfinite(rel) || S.passes >= A.max_passes ||
-                                 S.iters_total >= A.max_iter;
-                if (!fin) init_inner(P, i0, j0, rho2);
-                if (owner) {
-                    S.rho2 = rho2;
-                    S.rel = rel;
-                    if (fin) {
-                        nxt.mode = BM_DONE;
-                        S.t_done = wall_clock64();
-                        S.needs = 0;
-                        __hip_atomic_fetch_add(&ctl->n_done, 1, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int q = 0; q < NT / 64; ++q) {
+                off += q < wid ? s_wcnt[q] : 0;
+                nact += s_wcnt[q];
+            }
+            if (act) s_list[off + __popcll(bal & ((1ull << lane) - 1ull))] = wt;
+            __syncthreads();
+            for (int e = 0; e < nact; ++e) {
+                const int w = s_list[e];
+                int p, i0, j0;
+                item_of(A, w, p, i0, j0, BX, BY);
+                const BProb& P = A.prob[p];
+                BState& S = A.state[p];
+                const BPhase cur = S.ph[cs];
+                const bool owner = w == P.item0 && threadIdx.x == 0;
+                BPhase nxt = cur;
+                if (cur.mode == BM_CG) {
+                    const int k = cur.kloc;
+                    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                    if (k == 0) {
+                        tile_fused<BX, BY, true>(P, i0, j0, 0.f, 0.f, 0, lds32, v);
+                        item_partial<5>(v, A.partF[0], w);
+                        nxt.kloc = 1;
                     } else {
-                        double ti = rel > 0.0 ? 0.5 * A.tol / rel : 0.5;
-                        ti = ti < 1e-5 ? 1e-5 : (ti > 0.5 ? 0.5 : ti);
-                        S.tol_in2 = ti * ti;
-                        nxt.mode = BM_CG;
-                        nxt.kloc = 0;
+                        if (p != cached) {
+                            problem_total<5>(A.partF[(k + 1) & 1], P.item0, P.nt, tot);
+                            cached = p;
+                        }
+                        const double rz = tot[0], pq = tot[1], qdr = tot[2], qdq = tot[3], rrk = tot[4];
+                        const double bb = k == 1 ? rrk : S.bb;
+                        const bool stop = !isfinite(rz) || !isfinite(rrk) || !isfinite(pq) ||
+                                          rrk <= S.tol_in2 * bb || k - 1 >= A.max_iter_pass ||
+                                          S.iters_total + k - 1 >= A.max_iter || !(pq > 0.0);
+                        if (stop) {
+                            if (owner) {
+                                S.last_iter = k - 1;
+                                nxt.mode = BM_AXPY;
+                            }
+                        } else {
+                            const double ad = rz / pq;
+                            const double rzn = rz - 2.0 * ad * qdr + ad * ad * qdq;
+                            const double bd = rz > 0.0 ? rzn / rz : 0.0;
+                            tile_fused<BX, BY, false>(P, i0, j0, (float)ad, (float)bd, k, lds32, v);
+                            item_partial<5>(v, A.partF[k & 1], w);
+                            if (owner && k == 1) S.bb = bb;
+                            nxt.kloc = k + 1;
+                        }
+                    }
+                } else if (cur.mode == BM_AXPY) {
+                    const double rho = sqrt(S.rho2);
+                    for (int e = threadIdx.x; e < BX * BY; e += NT) {
+                        const int i = i0 + e % BX, j = j0 + e / BX;
+                        if (i > P.g.nx || j > P.g.ny) continue;
+                        const long long o = P.g.idx(i, j);
+#pragma unroll
+                        for (int s = 0; s < 3; ++s)
+                            P.x64[o + s * P.g.NP] += rho * (double)P.x32[o + s * P.g.NP];
+                    }
+                    if (owner) {
+                        S.iters_total += S.last_iter;
+                        S.passes += 1;
+                    }
+                    nxt.mode = BM_RESID;
+                } else if (cur.mode == BM_RESID) {
+                    double v[1];
+                    v[0] = tile_resid<BX, BY>(P.g, i0, j0, P.x64, P.r64, P.a64, P.c64, P.K64, P.b64,
+                                              lds64);
+                    item_partial<1>(v, A.partR, w);
+                    nxt.mode = BM_DECIDE;
+                } else if (cur.mode == BM_DECIDE && retire_phase) {
+                    double t1[1];
+                    problem_total<1>(A.partR, P.item0, P.nt, t1);
+                    const double rho2 = t1[0];
+                    const double rel = S.bb64 > 0.0 ? sqrt(rho2 / S.bb64) : 0.0;
+                    const bool fin = !(rel > A.tol) || !isfinite(rel) || S.passes >= A.max_passes ||
+                                     S.iters_total >= A.max_iter;
+                    if (!fin) init_inner(P, i0, j0, rho2);
+                    if (owner) {
+                        S.rho2 = rho2;
+                        S.rel = rel;
+                        if (fin) {
+                            nxt.mode = BM_DONE;
+                            S.t_done = wall_clock64();
+                            S.needs = 0;
+                            S.retired = 1;
+                            __hip_atomic_fetch_add(&ctl->n_done, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            double ti = rel > 0.0 ? 0.5 * A.tol / rel : 0.5;
+                            ti = ti < 1e-5 ? 1e-5 : (ti > 0.5 ? 0.5 : ti);
+                            S.tol_in2 = ti * ti;
+                            nxt.mode = BM_CG;
+                            nxt.kloc = 0;
+                        }
                     }
                 }
+                if (owner) S.ph[ns] = nxt;
             }
-            if (owner) S.ph[ns] = nxt;
+            __syncthreads();   // s_list and s_wcnt are rewritten by the next round
         }
         // retirements happen only in odd phases: the count is stable in even ones
         const int nd = retire_phase ? 0

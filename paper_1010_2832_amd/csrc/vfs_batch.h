@@ -39,6 +39,7 @@ struct BState {
     double rel;       // FP64 true relative residual
     double tol_in2;   // inner (FP32) relative tolerance squared for the next pass
     int needs;        // 1: the problem needs a solve (set before the persistent launch)
+    int retired;      // 1 once the problem is DONE (read when gathering a phase's items)
     int last_iter;    // iterations of the last inner solve
     int iters_total;  // iterations over all passes
     int passes;
