@@ -168,34 +168,46 @@ __global__ __launch_bounds__(CT) void k_conv3(ConvArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// 16 -> 16 channel convolution (the full-resolution layers): z-marching with
-// the input planes staged in LDS.  With 16 output channels a voxel operand
-// feeds a single MFMA, so operand bandwidth bounds the layer; here each input
-// plane is read from global memory once per tile (plus its x,y halo) and the
-// 27 taps read their operands from LDS, while the 14 weight operands of a
-// lane stay in registers for the whole launch.
+// Convolutions with 16 or 32 channels on each side (the full-resolution and
+// half-resolution layers): z-marching with the input planes staged in LDS.
+// With few output channels a voxel operand feeds only COUT / 16 MFMAs, so
+// operand bandwidth bounds these layers, not the matrix cores; here each
+// input plane is read from global memory once per tile (plus its x,y halo)
+// and the 27 taps read their operands from LDS, while the weight operands of
+// a lane stay in registers for the whole launch.
 //
-// Workgroup: a 32 x 8 voxel tile in x,y marching Z16 planes in z.  LDS holds
-// a ring of 4 input planes of 34 x 10 voxels, each split into two arrays of 8
-// channels (16 bytes per voxel, so the 16 lanes of one MFMA column group read
-// 256 contiguous bytes).  Step z: issue the global loads of plane z+2,
-// compute output plane z from the planes z-1, z, z+1, write the epilogue,
-// store plane z+2 into its slot (which held plane z-2), one barrier.
-// K = 32 kc + 8 kq + j covers taps t = 2 kc + kq / 2 with channels
-// 8 (kq % 2) + j, so the lanes 0-31 of a wave read one tap and lanes 32-63
-// the next; tap 27 (kc = 13, kq >= 2) is the zero padding of K.
+// Workgroup: a 32 x ZY voxel tile in x,y marching kZZ planes in z.  LDS holds
+// a ring of 4 input planes of 34 x (ZY + 2) voxels, each split into CIN / 8
+// arrays of 8 channels (16 bytes per voxel, so the 16 lanes of one MFMA
+// column group read 256 contiguous bytes).  Step z: issue the global loads of
+// plane z+2, compute output plane z from the planes z-1, z, z+1, write the
+// epilogue, store plane z+2 into its slot (which held plane z-2), one
+// barrier.  K = 32 kc + 8 kq + j is tap t = K / CIN, channel K % CIN: with 16
+// input channels lanes 0-31 of a wave read tap 2 kc and lanes 32-63 tap
+// 2 kc + 1 (tap 27, for kc = 13 and kq >= 2, is the zero padding of K); with
+// 32 they all read tap kc, 8 channels per lane group.
 // ---------------------------------------------------------------------------
-constexpr int kZX = 32, kZY = 8, kZZ = 16;            // output tile
-constexpr int kZHX = kZX + 2, kZHY = kZY + 2;          // input plane with halo
-constexpr int kZPlane = kZHX * kZHY;                   // voxels per input plane
-constexpr int kZChunks = 2 * kZPlane;                  // 16-byte chunks per plane
-constexpr int kZLoads = (kZChunks + CT - 1) / CT;      // chunks per thread
+constexpr int kZX = 32, kZZ = 16;   // output tile in x and z (ZY in y)
 
-template <int EPI>
-__global__ __launch_bounds__(CT) void k_conv3_z16(ConvArgs A, int ntx, int nty, int ntz) {
+template <int CIN, int ZY>
+struct ZTile {
+    static constexpr int HX = kZX + 2, HY = ZY + 2;
+    static constexpr int PLANE = HX * HY;                 // voxels per input plane
+    static constexpr int OCT = CIN / 8;                   // 16-byte channel octets per voxel
+    static constexpr int CHUNKS = OCT * PLANE;            // 16-byte chunks per plane
+    static constexpr int LOADS = (CHUNKS + CT - 1) / CT;  // chunks per thread
+    static constexpr int NVW = ZY / 2;                    // 16-voxel column groups per wave
+};
+
+template <int CIN, int COUT, int ZY, int EPI>
+__global__ __launch_bounds__(CT) void k_conv3_z(ConvArgs A, int ntx, int nty, int ntz) {
     if (A.skip && *A.skip) return;
-    constexpr int KP = conv_kp(16), NKC = KP / 32;
-    __shared__ __align__(16) uint4 sIn[4][2][kZPlane];
+    using Z = ZTile<CIN, ZY>;
+    static_assert(CIN == 16 || CIN == 32, "input channels");
+    static_assert(COUT % 16 == 0 && ZY % 4 == 0, "tile");
+    constexpr int KP = conv_kp(CIN), NKC = KP / 32, MT = COUT / 16;
+    constexpr int NVW = Z::NVW, HX = Z::HX;
+    __shared__ __align__(16) uint4 sIn[4][Z::OCT][Z::PLANE];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, n = lane & 15;
     const Level L = A.L;
@@ -207,38 +219,41 @@ __global__ __launch_bounds__(CT) void k_conv3_z16(ConvArgs A, int ntx, int nty, 
         tile = x8 * q + min(x8, rem) + (b >> 3);
     }
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-    const int x0 = tx * kZX, y0 = ty * kZY, z0 = tz * kZZ;
+    const int x0 = tx * kZX, y0 = ty * ZY, z0 = tz * kZZ;
     const int zend = min(z0 + kZZ, L.Z);
 
-    // weight operands: row co = n, K = 32 kc + 8 kq .. +7
-    bf16x8 a[NKC];
+    // weight operands: row co = 16 mt + n, K = 32 kc + 8 kq .. +7
+    bf16x8 a[NKC][MT];
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc) a[kc] = ld16(A.w + (long long)n * KP + kc * 32 + kq * 8);
+    for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            a[kc][mt] = ld16(A.w + (long long)(16 * mt + n) * KP + kc * 32 + kq * 8);
 
-    // plane loader: chunk e = 2 * voxel + half of the 34 x 10 input plane
-    auto fetch = [&](int zz, uint4 (&r)[kZLoads]) {
+    // plane loader: chunk e = OCT * voxel + octet of the input plane
+    auto fetch = [&](int zz, uint4 (&r)[Z::LOADS]) {
 #pragma unroll
-        for (int m = 0; m < kZLoads; ++m) {
+        for (int m = 0; m < Z::LOADS; ++m) {
             const int e = threadIdx.x + m * CT;
             r[m] = uint4{0u, 0u, 0u, 0u};
-            if (e < kZChunks) {
-                const int v = e >> 1, h = e & 1;
-                const int x = x0 - 1 + v % kZHX, y = y0 - 1 + v / kZHX;
+            if (e < Z::CHUNKS) {
+                const int v = e / Z::OCT, h = e % Z::OCT;
+                const int x = x0 - 1 + v % HX, y = y0 - 1 + v / HX;
                 if (x <= L.X && y <= L.Y && zz <= L.Z)
-                    r[m] = *reinterpret_cast<const uint4*>(A.in + L.off(x, y, zz) * 16 + h * 8);
+                    r[m] = *reinterpret_cast<const uint4*>(A.in + L.off(x, y, zz) * CIN + h * 8);
             }
         }
     };
-    auto commit = [&](int zz, const uint4 (&r)[kZLoads]) {
+    auto commit = [&](int zz, const uint4 (&r)[Z::LOADS]) {
         const int sl = (zz + 4) & 3;
 #pragma unroll
-        for (int m = 0; m < kZLoads; ++m) {
+        for (int m = 0; m < Z::LOADS; ++m) {
             const int e = threadIdx.x + m * CT;
-            if (e < kZChunks) sIn[sl][e & 1][e >> 1] = r[m];
+            if (e < Z::CHUNKS) sIn[sl][e % Z::OCT][e / Z::OCT] = r[m];
         }
     };
 
-    uint4 pre[kZLoads];
+    uint4 pre[Z::LOADS];
     fetch(z0 - 1, pre);
     commit(z0 - 1, pre);
     fetch(z0, pre);
@@ -247,56 +262,63 @@ __global__ __launch_bounds__(CT) void k_conv3_z16(ConvArgs A, int ntx, int nty, 
     commit(z0 + 1, pre);
     __syncthreads();
 
-    // this wave's four 16-voxel column groups: rows yr, x offsets xo
     const bf16x8 zero8 = __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
     for (int z = z0; z < zend; ++z) {
         const bool more = z + 2 <= zend;
         if (more) fetch(z + 2, pre);
-        f32x4 acc[4];
+        f32x4 acc[NVW][MT];
 #pragma unroll
-        for (int nv = 0; nv < 4; ++nv) acc[nv] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nv = 0; nv < NVW; ++nv)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[nv][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
-            const int t = 2 * kc + (kq >> 1);
+            const int K = 32 * kc + 8 * kq;
+            const int t = K / CIN, oct = (K % CIN) / 8;
             const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-            const uint4* pl = sIn[(z + dz - 1 + 4) & 3][kq & 1];
+            const uint4* pl = sIn[(z + dz - 1 + 4) & 3][oct];
 #pragma unroll
-            for (int nv = 0; nv < 4; ++nv) {
-                const int yr = 2 * wave + (nv >> 1), xo = 16 * (nv & 1);
-                const bf16x8 bo = t < 27 ? __builtin_bit_cast(bf16x8, pl[(yr + dy) * kZHX + xo + n + dx])
+            for (int nv = 0; nv < NVW; ++nv) {
+                const int yr = (ZY / 4) * wave + (nv >> 1), xo = 16 * (nv & 1);
+                const bf16x8 bo = t < 27 ? __builtin_bit_cast(bf16x8, pl[(yr + dy) * HX + xo + n + dx])
                                          : zero8;
-                acc[nv] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc], bo, acc[nv], 0, 0, 0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[nv][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kc][mt], bo, acc[nv][mt], 0, 0, 0);
             }
         }
-        // epilogue: lane holds output channels 4 kq .. +3 of voxel n
+        // epilogue: lane holds output channels 16 mt + 4 kq .. +3 of voxel n
 #pragma unroll
-        for (int nv = 0; nv < 4; ++nv) {
-            const int yr = 2 * wave + (nv >> 1), xo = 16 * (nv & 1);
+        for (int nv = 0; nv < NVW; ++nv) {
+            const int yr = (ZY / 4) * wave + (nv >> 1), xo = 16 * (nv & 1);
             const int x = x0 + xo + n, y = y0 + yr;
             if (x >= L.X || y >= L.Y) continue;
-            const int co0 = 4 * kq;
-            float o[4] = {acc[nv][0], acc[nv][1], acc[nv][2], acc[nv][3]};
-            if (EPI == EPI_F32) {
-                if (co0 < 8) {
-                    const long long v = ((long long)z * L.Y + y) * L.X + x;
-                    *reinterpret_cast<float4*>(A.out32 + v * 8 + co0) = float4{o[0], o[1], o[2], o[3]};
-                }
-                continue;
-            }
             const long long vo = L.off(x, y, z);
-            if (EPI == EPI_RELU) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = fmaxf(o[i], 0.f);
-            } else if (EPI == EPI_MASK) {
-                const uint2 mk = *reinterpret_cast<const uint2*>(A.mask + vo * 16 + co0);
-                const uint32_t mw[4] = {mk.x & 0xffffu, mk.x >> 16, mk.y & 0xffffu, mk.y >> 16};
+            for (int mt = 0; mt < MT; ++mt) {
+                const int co0 = 16 * mt + 4 * kq;
+                float o[4] = {acc[nv][mt][0], acc[nv][mt][1], acc[nv][mt][2], acc[nv][mt][3]};
+                if (EPI == EPI_F32) {
+                    if (co0 < 8) {
+                        const long long v = ((long long)z * L.Y + y) * L.X + x;
+                        *reinterpret_cast<float4*>(A.out32 + v * 8 + co0) = float4{o[0], o[1], o[2], o[3]};
+                    }
+                    continue;
+                }
+                if (EPI == EPI_RELU) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) o[i] = bf2f(mw[i]) > 0.f ? o[i] : 0.f;
+                    for (int i = 0; i < 4; ++i) o[i] = fmaxf(o[i], 0.f);
+                } else if (EPI == EPI_MASK) {
+                    const uint2 mk = *reinterpret_cast<const uint2*>(A.mask + vo * COUT + co0);
+                    const uint32_t mw[4] = {mk.x & 0xffffu, mk.x >> 16, mk.y & 0xffffu, mk.y >> 16};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) o[i] = bf2f(mw[i]) > 0.f ? o[i] : 0.f;
+                }
+                uint2 st;
+                st.x = f2bf(o[0]) | (f2bf(o[1]) << 16);
+                st.y = f2bf(o[2]) | (f2bf(o[3]) << 16);
+                *reinterpret_cast<uint2*>(A.out + vo * COUT + co0) = st;
             }
-            uint2 st;
-            st.x = f2bf(o[0]) | (f2bf(o[1]) << 16);
-            st.y = f2bf(o[2]) | (f2bf(o[3]) << 16);
-            *reinterpret_cast<uint2*>(A.out + vo * 16 + co0) = st;
         }
         // plane z + 2 replaces plane z - 2, which no wave reads any more
         if (more) commit(z + 2, pre);
@@ -304,13 +326,14 @@ __global__ __launch_bounds__(CT) void k_conv3_z16(ConvArgs A, int ntx, int nty, 
     }
 }
 
-template <int EPI>
-void conv_launch_z16(const ConvArgs& a, hipStream_t s) {
-    const int ntx = (a.L.X + kZX - 1) / kZX, nty = (a.L.Y + kZY - 1) / kZY;
+template <int CIN, int COUT, int ZY, int EPI>
+void conv_launch_z(const ConvArgs& a, hipStream_t s) {
+    const int ntx = (a.L.X + kZX - 1) / kZX, nty = (a.L.Y + ZY - 1) / ZY;
     const int ntz = (a.L.Z + kZZ - 1) / kZZ;
     const long long nb = (long long)ntx * nty * ntz;
     if (nb == 0) return;
-    hipLaunchKernelGGL((k_conv3_z16<EPI>), dim3((unsigned)nb), dim3(CT), 0, s, a, ntx, nty, ntz);
+    hipLaunchKernelGGL((k_conv3_z<CIN, COUT, ZY, EPI>), dim3((unsigned)nb), dim3(CT), 0, s, a, ntx,
+                       nty, ntz);
 }
 
 template <int CIN, int COUT, int EPI>
@@ -875,21 +898,24 @@ bool launch_conv3(int cin, int cout, int epi, const ConvArgs& a, hipStream_t s) 
         }                                                                         \
         return false;                                                             \
     }
-    if (cin == 16 && cout == 16) {
-        switch (epi) {
-            case EPI_RELU: conv_launch_z16<EPI_RELU>(a, s); return true;
-            case EPI_PLAIN: conv_launch_z16<EPI_PLAIN>(a, s); return true;
-            case EPI_MASK: conv_launch_z16<EPI_MASK>(a, s); return true;
-            case EPI_F32: conv_launch_z16<EPI_F32>(a, s); return true;
-        }
-        return false;
+#define VFS_CONVZ(CI, CO, ZY)                                                         \
+    if (cin == CI && cout == CO) {                                                     \
+        switch (epi) {                                                                 \
+            case EPI_RELU: conv_launch_z<CI, CO, ZY, EPI_RELU>(a, s); return true;     \
+            case EPI_PLAIN: conv_launch_z<CI, CO, ZY, EPI_PLAIN>(a, s); return true;   \
+            case EPI_MASK: conv_launch_z<CI, CO, ZY, EPI_MASK>(a, s); return true;     \
+            case EPI_F32: conv_launch_z<CI, CO, ZY, EPI_F32>(a, s); return true;       \
+        }                                                                              \
+        return false;                                                                  \
     }
-    VFS_CONV(16, 32)
+    VFS_CONVZ(16, 16, 8)
+    VFS_CONVZ(16, 32, 8)
+    VFS_CONVZ(32, 16, 4)
+#undef VFS_CONVZ
     VFS_CONV(32, 64)
     VFS_CONV(64, 128)
     VFS_CONV(128, 64)
     VFS_CONV(64, 32)
-    VFS_CONV(32, 16)
 #undef VFS_CONV
     return false;
 }
