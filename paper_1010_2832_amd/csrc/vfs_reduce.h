@@ -15,10 +15,30 @@
 
 namespace vfs {
 
+// DPP move of a double (both 32-bit halves) with the given control word; lanes
+// whose source lies outside their row, or rows outside ROWS, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave (all lanes active), returned in every lane.
+// Row prefix sums by row_shr 1, 2, 4, 8 leave each 16-lane row's sum in its
+// lane 15; row_bcast 15 adds row 0 into row 1 and row 2 into row 3, and
+// row_bcast 31 adds lane 31 into rows 2 and 3, so lane 63 holds the total.
+// Register moves only (no LDS crossbar), in a fixed order.
 __device__ __forceinline__ double wave_sum64(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Writes this workgroup's sums of v[] to part[q * nb + bid].
