@@ -93,21 +93,18 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
         const int i = i0 - 1 + li, j = j0 - 1 + lj;
         in1[m] = e < (BX + 2) * (BY + 2) && i <= g.nx + 1 && j <= g.ny + 1;
         own1[m] = in1[m] && li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
+        // positions outside the grid read offset 0 of each slice, its zero pad
         const long long o = in1[m] ? g.idx(i, j) : 0;
+        const long long ox = own1[m] ? o : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const long long os = o + s * NP;
-            Rr[m][s] = Dd[m][s] = Qq[m][s] = Pp[m][s] = Aa[m][s] = Xx[m][s] = T(0);
-            if (in1[m]) {
-                Rr[m][s] = r_in[os];
-                Dd[m][s] = dinv[os];
-                Aa[m][s] = a[os];
-                if (!INIT) {
-                    Qq[m][s] = q_in[os];
-                    Pp[m][s] = p_in[os];
-                }
-            }
-            if (!INIT && own1[m]) Xx[m][s] = x[os];
+            Rr[m][s] = r_in[os];
+            Dd[m][s] = dinv[os];
+            Aa[m][s] = a[os];
+            Qq[m][s] = INIT ? T(0) : q_in[os];
+            Pp[m][s] = INIT ? T(0) : p_in[os];
+            Xx[m][s] = INIT ? T(0) : x[ox + s * NP];
         }
     }
     T Ku[NE2], Kv[NE2];
@@ -115,13 +112,13 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     for (int m = 0; m < NE2; ++m) {
         const int e = tid + m * NT;
         const int li = e % (BX + 1), lj = e / (BX + 1);
-        Ku[m] = Kv[m] = T(0);
-        if (e < (BX + 1) * (BY + 1)) {
-            const int iu = i0 + li, ju = j0 - 1 + lj;
-            if (iu <= g.nx && ju >= 0 && ju < g.ny) Ku[m] = K[g.idx(iu, ju)];
-            const int iv = i0 - 1 + li, jv = j0 + lj;
-            if (iv >= 0 && iv < g.nx && jv <= g.ny) Kv[m] = K[NP + g.idx(iv, jv)];
-        }
+        const bool fe = e < (BX + 1) * (BY + 1);
+        const int iu = i0 + li, ju = j0 - 1 + lj;
+        const int iv = i0 - 1 + li, jv = j0 + lj;
+        const bool okU = fe && iu <= g.nx && ju >= 0 && ju < g.ny;
+        const bool okV = fe && iv >= 0 && iv < g.nx && jv <= g.ny;
+        Ku[m] = K[okU ? g.idx(iu, ju) : 0];
+        Kv[m] = K[NP + (okV ? g.idx(iv, jv) : 0)];
     }
     const int tx = tid % BX;
     T Ao[RPT][3], Co[RPT][2];
@@ -132,9 +129,9 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
         const bool ok = i <= g.nx && j <= g.ny;
         const long long o = ok ? g.idx(i, j) : 0;
 #pragma unroll
-        for (int s = 0; s < 3; ++s) Ao[rr][s] = ok ? a[o + s * NP] : T(0);
-        Co[rr][0] = ok ? c[NP + o] : T(0);
-        Co[rr][1] = ok ? c[2 * NP + o] : T(0);
+        for (int s = 0; s < 3; ++s) Ao[rr][s] = a[o + s * NP];
+        Co[rr][0] = c[NP + o];
+        Co[rr][1] = c[2 * NP + o];
     }
 
     // (3) totals of iteration k-1 -> stop decision, alpha_{k-1}, beta_k.  The
