@@ -37,7 +37,7 @@ constexpr int NT = 256;
 
 __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks) {
     // every wave's global stores are acknowledged by L2 before thread 0
-    // publishes them (agent-scope release: L2 write-back for the other XCDs)
+    // publishes them
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     __shared__ int s_abort;
@@ -45,14 +45,26 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks) {
         // the generation is read (and waited for) before arriving
         const unsigned my_gen =
             __hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // two-level arrival: group counter, then (last of the group) the top
+        // counter; acquire-release RMWs chain every workgroup's writes to the
+        // one that advances the generation (agent scope: L2 write-back for
+        // the other XCDs)
+        const unsigned gi = blockIdx.x % kBarGroups;
+        const unsigned ngrp = nblocks < (unsigned)kBarGroups ? nblocks : (unsigned)kBarGroups;
+        const unsigned gsz = (nblocks - gi + kBarGroups - 1) / kBarGroups;
+        unsigned* grp = &ctl->bar_grp[gi * kBarStride];
         int abort = 0;
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        bool advanced = false;
+        if (__hip_atomic_fetch_add(grp, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gsz - 1) {
+            __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                       __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1) {
+                __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&ctl->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                advanced = true;
+            }
+        }
+        if (!advanced) {
             const unsigned long long deadline = wall_clock64() + ctl->spin_ticks;
             // relaxed polling: coherent loads without cache invalidation
             while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
@@ -450,12 +462,14 @@ __global__ __launch_bounds__(NT) void k_batch_zero_x(BatchArgs A) {
 // Resets the barrier / counters of the persistent kernel (a kernel, not a
 // memset, so that it can live in a captured graph).
 __global__ void k_batch_reset_ctl(BatchCtl* ctl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0) {
         ctl->bar_count = 0;
         ctl->abort = 0;
         ctl->n_done = 0;
         ctl->n_need = 0;
     }
+    if (threadIdx.x < kBarGroups) ctl->bar_grp[threadIdx.x * kBarStride] = 0;
 }
 
 // The persistent solve of every problem, refinement included.  One phase per

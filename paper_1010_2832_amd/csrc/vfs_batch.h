@@ -46,14 +46,19 @@ struct BState {
     unsigned long long t_start, t_done;   // device wall clock
 };
 
+// Grid barrier: workgroup b arrives at group counter b % kBarGroups, the last
+// arrival of each group at the top counter, the last of those advances the
+// generation.  Group counters sit kBarStride words apart (own cache lines).
+constexpr int kBarGroups = 16, kBarStride = 32;
 struct BatchCtl {
-    unsigned bar_count;
+    unsigned bar_count;   // top-level arrivals
     unsigned bar_gen;
     int abort;
     int n_done;
     int n_need;
     int pad;
     unsigned long long spin_ticks;   // barrier wait deadline (wall-clock ticks)
+    unsigned bar_grp[kBarGroups * kBarStride];
 };
 
 struct BatchArgs {
