@@ -126,6 +126,54 @@ def config3_leg(V):
     return out
 
 
+def config4_leg(V, check=True):
+    """Many uneven 2D solves in one persistent, graph-captured launch: the 64
+    problems of sizes {64, 96, ..., 512}^2, tile shape and workgroups per CU
+    picked by the autotuner, mixed precision to 1e-6.  Reports the solve time,
+    aggregate DOF*iter/s, per-problem latency percentiles and, unless check is
+    off, the smallest problem's velocity against the FP64 oracle."""
+    import numpy as np
+    import cases
+    from paper_1010_2832_amd import autotune
+    probs = cases.config4()
+    sizes = [c["n"][0] for c in probs]
+    b = V.batch_from_cases(probs, tol=1e-6)
+    b.vfs_batch_step(probs[0]["dt"])          # first step: warms the code paths up
+    tune = autotune.tune(b, iterations=20, use_cache=False, cache_path=None)
+    for i, c in enumerate(probs):                # the timed step starts again from u^0
+        b.vfs_batch_set_problem(i, c)
+    b.vfs_batch_step(probs[0]["dt"])
+    st = b.vfs_batch_get_stats()
+    per = [b.vfs_batch_get_problem(i) for i in range(len(probs))]
+    out = {"workload": f"{len(probs)} 2D problems shaped as the 32^2 drop case, sizes "
+                       f"{{64, 96, ..., 512}}^2 drawn with seed 4 ({min(sizes)}..{max(sizes)}), "
+                       "mixed Jacobi PCG to 1e-6, one persistent launch per step",
+           "status": st["status"], "n_problems": st["n_problems"],
+           "n_active_total": st["n_active_total"], "dof_iters": st["dof_iters"],
+           "solve_ms": st["t_solve_ms"], "step_ms": st["t_step_ms"],
+           "dof_iter_per_s": st["dof_iters"] / (st["t_solve_ms"] * 1e-3),
+           "latency_ms": {"p50": st["latency_p50_ms"], "p90": st["latency_p90_ms"],
+                          "p99": st["latency_p99_ms"], "max": st["latency_max_ms"]},
+           "autotune": {"shape": tune["shape"], "blocks_per_cu": tune["blocks_per_cu"],
+                        "ms_per_iteration": tune["ms_per_iteration"]},
+           "grid": st["grid"], "graph_used": bool(st["graph_used"]),
+           "max_rel_residual_fp64": max(p["rel_residual"] for p in per),
+           "max_iterations": st["max_iterations"]}
+    if check:
+        from oracle import system
+        i = int(np.argmin(sizes))
+        asm, x, u = system.step(probs[i])
+        ug = np.concatenate([asm.grid.flat(q) for q in b.vfs_batch_get_velocity(i)])
+        m = asm.K > 0
+        out["error_vs_fp64_oracle"] = {
+            "problem": i, "n": sizes[i],
+            "velocity_rel_linf": float(np.abs(ug[m] - u[m]).max() / np.abs(u[m]).max()),
+            "rel_residual_measured_by_oracle": float(
+                system.true_relative_residual(asm, b.vfs_batch_get_solution(i)))}
+    b.close()
+    return out
+
+
 def config5_leg(V, learned_cap=400):
     """Learned vs plain PCG on the 3D 256^3 configuration: Jacobi PCG in mixed
     precision to 1e-6, then truncated flexible CG with the committed network
@@ -181,6 +229,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=400)
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the 128^3 FP64-vs-mixed leg")
+    ap.add_argument("--no-config4", action="store_true",
+                    help="skip the batched 64-problem 2D leg")
     ap.add_argument("--no-config5", action="store_true",
                     help="skip the 256^3 learned-vs-plain leg")
     args = ap.parse_args()
@@ -293,6 +343,8 @@ def main():
     ctx.close()
     if not args.no_config3:
         out["config3_fp64_vs_mixed"] = config3_leg(V)
+    if not args.no_config4:
+        out["config4_batched"] = config4_leg(V, check=not args.no_check)
     if not args.no_config5:
         out["config5_learned_vs_plain"] = config5_leg(V)
     print(json.dumps(out), flush=True)

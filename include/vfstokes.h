@@ -228,6 +228,9 @@ typedef struct vfs_batch_stats {
     double  latency_p50_ms, latency_p90_ms, latency_p99_ms, latency_max_ms;
                               /* per-problem solve latency: device wall clock from
                                  the start of the solve to the pass that met tol */
+    int64_t n_items;          /* work items of the last step: the tiles holding an
+                                 active sample (at least one per problem) */
+    int64_t n_tile_samples;   /* sample positions those items sweep per CG iteration */
 } vfs_batch_stats;
 
 const char* vfs_batch_last_error(const vfs_batch* b);

@@ -2,8 +2,10 @@
 // persistent launch.
 //
 // Every problem has its own padded arrays (assembled by the single-problem
-// kernels).  Work items are (problem, 2D tile) pairs, dealt round-robin over
-// the workgroups.  One persistent kernel runs the whole
+// kernels).  Work items are (problem, 2D tile) pairs over the tiles holding
+// an active sample, rebuilt after each assembly and dealt round-robin over
+// the workgroups; the other tiles' vectors are zeroed at the start of the
+// solve and never touched.  One persistent kernel runs the whole
 // mixed-precision solve of every problem: FP32 Jacobi-PCG inner solves and
 // FP64 iterative refinement, as a per-problem state machine whose phases are
 // separated by a grid barrier.  An inner CG iteration takes one phase: the
@@ -387,7 +389,7 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
 __device__ __forceinline__ void item_of(const BatchArgs& A, int w, int& p, int& i0, int& j0,
                                         int bx, int by) {
     p = A.item_prob[w];
-    const int t = w - A.prob[p].item0;
+    const int t = A.item_tile[w];
     const int ntx = A.prob[p].ntx;
     i0 = (t % ntx) * bx;
     j0 = (t / ntx) * by;
@@ -398,7 +400,8 @@ template <int BX, int BY>
 __global__ __launch_bounds__(NT) void k_batch_resid(BatchArgs A) {
     extern __shared__ double lds_dyn[];
     double* lds64 = lds_dyn;
-    for (int w = blockIdx.x; w < A.nitems; w += gridDim.x) {
+    const int nitems = *A.nlive;
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         int p, i0, j0;
         item_of(A, w, p, i0, j0, BX, BY);
         const BProb& P = A.prob[p];
@@ -441,21 +444,50 @@ __global__ __launch_bounds__(NT) void k_batch_finalize(BatchArgs A) {
 }
 
 // x64 = 0 for every problem (first pass)
-__global__ __launch_bounds__(NT) void k_batch_zero_x(BatchArgs A) {
-    for (int w = blockIdx.x; w < A.nitems; w += gridDim.x) {
-        int p, i0, j0;
-        item_of(A, w, p, i0, j0, A.bx, A.by);
-        const BProb& P = A.prob[p];
-        if (w == P.item0 && threadIdx.x == 0) {
-            A.state[p].t_start = wall_clock64();
-            A.state[p].needs = 0;
+// Start of a solve: zeroes the solution and every CG vector of problem
+// blockIdx.y over its whole arrays, so that tiles outside the active list
+// (read as halo by their active neighbours) hold zeros, and stamps the start
+// time.
+__global__ __launch_bounds__(NT) void k_batch_zero(BatchArgs A) {
+    const int p = blockIdx.y;
+    const BProb& P = A.prob[p];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.state[p].t_start = wall_clock64();
+        A.state[p].needs = 0;
+    }
+    const long long n = 3 * P.g.NP;
+    for (long long e = (long long)blockIdx.x * NT + threadIdx.x; e < n;
+         e += (long long)gridDim.x * NT) {
+        P.x64[e] = 0.0;
+        P.r64[e] = 0.0;
+        P.x32[e] = 0.f;
+        P.r32[e] = 0.f;
+        P.r32b[e] = 0.f;
+        P.p0[e] = 0.f;
+        P.p1[e] = 0.f;
+        P.q32[e] = 0.f;
+        P.q32b[e] = 0.f;
+    }
+}
+
+// Tile f of the list of all tiles is active if any sample anchored in it has
+// a != 0 (the same test as the single-problem tile lists).
+__global__ __launch_bounds__(NT) void k_batch_tile_flags(const BProb* __restrict__ prob,
+                                                         const int* __restrict__ full_prob,
+                                                         int nfull, int bx, int by,
+                                                         int* __restrict__ flags) {
+    for (int f = blockIdx.x; f < nfull; f += gridDim.x) {
+        const BProb& P = prob[full_prob[f]];
+        const int t = f - P.full0;
+        const int i0 = (t % P.ntx) * bx, j0 = (t / P.ntx) * by;
+        int any = 0;
+        for (int e = threadIdx.x; e < bx * by; e += NT) {
+            const int i = i0 + e % bx, j = j0 + e / bx;
+            if (i <= P.g.nx && j <= P.g.ny)
+                for (int s = 0; s < 3; ++s) any |= P.a64[s * P.g.NP + P.g.idx(i, j)] != 0.0;
         }
-        for (int e = threadIdx.x; e < A.bx * A.by; e += NT) {
-            const int i = i0 + e % A.bx, j = j0 + e / A.bx;
-            if (i > P.g.nx || j > P.g.ny) continue;
-            const long long o = P.g.idx(i, j);
-            for (int s = 0; s < 3; ++s) P.x64[o + s * P.g.NP] = 0.0;
-        }
+        any = __syncthreads_or(any);
+        if (threadIdx.x == 0) flags[f] = any;
     }
 }
 
@@ -495,6 +527,7 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     // problem's tiles are spread over the whole grid and the problems still
     // iterating near the end of a solve keep every workgroup busy
     const int wb = (int)blockIdx.x, ws = (int)G;
+    const int nitems = *A.nlive;
 
     // r32 = r64 / |r64|, x32 = 0 on the tile (start of an inner solve)
     auto init_inner = [&](const BProb& P, int i0, int j0, double rho2) {
@@ -513,7 +546,7 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
     };
 
     // phase "-1": initial modes
-    for (int w = wb; w < A.nitems; w += ws) {
+    for (int w = wb; w < nitems; w += ws) {
         int p, i0, j0;
         item_of(A, w, p, i0, j0, BX, BY);
         const BProb& P = A.prob[p];
@@ -541,9 +574,9 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
         // gather this workgroup's items of problems that have not retired (up
         // to NT per round, in item order): the mode reads of all items are in
         // flight together instead of one dependent chain per item
-        for (int r0 = 0; wb + r0 * ws < A.nitems; r0 += NT) {
+        for (int r0 = 0; wb + r0 * ws < nitems; r0 += NT) {
             const int wt = wb + (r0 + (int)threadIdx.x) * ws;
-            const bool act = wt < A.nitems && !A.state[A.item_prob[wt]].retired;
+            const bool act = wt < nitems && !A.state[A.item_prob[wt]].retired;
             const unsigned long long bal = __ballot(act);
             const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
             if (lane == 0) s_wcnt[wid] = __popcll(bal);
@@ -707,8 +740,15 @@ void launch_batch_finalize(const BatchArgs& A, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_finalize, dim3(A.nprob), dim3(NT), 0, s, A);
 }
 
-void launch_batch_zero_x(const BatchArgs& A, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_zero_x, dim3(grid), dim3(NT), 0, s, A);
+void launch_batch_zero(const BatchArgs& A, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_zero, dim3(64, A.nprob), dim3(NT), 0, s, A);
+}
+
+void launch_batch_tile_flags(const BProb* prob, const int* full_prob, int nfull, int bx, int by,
+                             int* flags, hipStream_t s) {
+    if (nfull <= 0) return;
+    hipLaunchKernelGGL(k_batch_tile_flags, dim3(std::min(nfull, 8192)), dim3(NT), 0, s, prob,
+                       full_prob, nfull, bx, by, flags);
 }
 
 void launch_batch_reset_ctl(BatchCtl* ctl, hipStream_t s) {

@@ -11,7 +11,8 @@ constexpr int kBatchVariants = 4;   // tile shapes (BX x BY): 64x4, 64x8, 32x8, 
 // One problem as seen by the batched kernels (pointers into its context).
 struct BProb {
     Geo g;
-    int item0, nt, ntx, nty;      // first work item, tiles (items) of this problem
+    int item0, nt;                // first work item and item count of this step (active tiles)
+    int ntx, nty, full0;          // tile grid and first tile in the list of all tiles
     float *x32, *r32, *p0, *p1, *q32;
     float *r32b, *q32b;           // second r and q buffers (iteration parity)
     const float *a, *c, *K, *dinv;
@@ -61,12 +62,18 @@ struct BatchCtl {
     unsigned bar_grp[kBarGroups * kBarStride];
 };
 
+// Work items are the active tiles of every problem, rebuilt after each
+// assembly: item w is tile item_tile[w] of problem item_prob[w], a problem's
+// items are contiguous and in tile order, and *nlive holds their number (read
+// on the device, so a captured graph stays valid when the count changes).
 struct BatchArgs {
     BProb* prob;
     BState* state;
     BatchCtl* ctl;
     const int* item_prob;
-    int nitems, nprob;
+    const int* item_tile;
+    const int* nlive;
+    int nprob;
     double* partF[2];   // five CG partials per item, by iteration parity
     double* partR;      // FP64 |r64|^2 partial per item
     double tol;
@@ -81,7 +88,9 @@ int batch_pcg_occupancy(int variant, int* blocks_per_cu);
 void launch_batch_pcg(int variant, const BatchArgs& A, int grid, hipStream_t s);
 void launch_batch_resid(int variant, const BatchArgs& A, int grid, hipStream_t s);
 void launch_batch_finalize(const BatchArgs& A, hipStream_t s);
-void launch_batch_zero_x(const BatchArgs& A, int grid, hipStream_t s);
+void launch_batch_zero(const BatchArgs& A, hipStream_t s);
+void launch_batch_tile_flags(const BProb* prob, const int* full_prob, int nfull, int bx, int by,
+                             int* flags, hipStream_t s);
 void launch_batch_reset_ctl(BatchCtl* ctl, hipStream_t s);
 
 // single-problem pieces reused by the batch (vfs_api.hip)

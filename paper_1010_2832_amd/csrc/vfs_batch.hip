@@ -34,9 +34,15 @@ struct vfs_batch {
     BProb* d_prob = nullptr;
     BState* d_state = nullptr;
     BatchCtl* d_ctl = nullptr;
-    int* d_item_prob = nullptr;
+    int* d_item_prob = nullptr;   // live items (capacity nfull): problem, tile
+    int* d_item_tile = nullptr;
+    int* d_nlive = nullptr;       // live item count, read by the kernels
+    int* d_full_prob = nullptr;   // problem of each tile in the list of all tiles
+    int* d_flags = nullptr;       // active flag of each tile in that list
+    int* h_flags = nullptr;       // pinned staging: flags, then the live lists
     double* d_part = nullptr;
-    int nitems = 0;
+    int nfull = 0;                // tiles of all problems
+    int nlive = 0;                // items of the current step
     long long part_cap = 0;
     std::vector<BProb> h_prob;
     BState* h_state = nullptr;   // pinned
@@ -75,7 +81,8 @@ BatchArgs args(vfs_batch* b, int first_pass) {
     A.state = b->d_state;
     A.ctl = b->d_ctl;
     A.item_prob = b->d_item_prob;
-    A.nitems = b->nitems;
+    A.item_tile = b->d_item_tile;
+    A.nlive = b->d_nlive;
     A.nprob = b->n;
     A.partF[0] = b->d_part;
     A.partF[1] = b->d_part + 5 * b->part_cap;
@@ -89,11 +96,69 @@ BatchArgs args(vfs_batch* b, int first_pass) {
     return A;
 }
 
-// (re)build the work items for the current tile variant
+// Upload the live item lists (problem, tile) held in h_flags[nfull...] and
+// the per-problem item ranges; blocks until the copies are done.
+int upload_items(vfs_batch* b) {
+    hipStream_t s = b->stream;
+    const int* hp = b->h_flags + b->nfull;
+    const int* ht = hp + b->nfull;
+    BCHK(hipMemcpyAsync(b->d_item_prob, hp, sizeof(int) * b->nlive, hipMemcpyHostToDevice, s));
+    BCHK(hipMemcpyAsync(b->d_item_tile, ht, sizeof(int) * b->nlive, hipMemcpyHostToDevice, s));
+    b->h_flags[3 * b->nfull] = b->nlive;
+    BCHK(hipMemcpyAsync(b->d_nlive, b->h_flags + 3 * b->nfull, sizeof(int), hipMemcpyHostToDevice,
+                        s));
+    BCHK(hipMemcpyAsync(b->d_prob, b->h_prob.data(), sizeof(BProb) * b->n, hipMemcpyHostToDevice,
+                        s));
+    BCHK(hipStreamSynchronize(s));
+    return VFS_OK;
+}
+
+// Live items of the assembled step: the tiles of each problem holding an
+// active sample, in problem and tile order.  A problem without one keeps its
+// first tile, so that it still has an owner item (it retires at once).
+int compact_items(vfs_batch* b) {
+    hipStream_t s = b->stream;
+    int bx, by;
+    batch_tile_shape(b->variant, &bx, &by);
+    launch_batch_tile_flags(b->d_prob, b->d_full_prob, b->nfull, bx, by, b->d_flags, s);
+    BCHK(hipGetLastError());
+    BCHK(hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int) * b->nfull, hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    int* hp = b->h_flags + b->nfull;
+    int* ht = hp + b->nfull;
+    int n = 0;
+    for (int p = 0; p < b->n; ++p) {
+        BProb& P = b->h_prob[p];
+        P.item0 = n;
+        for (int t = 0; t < P.ntx * P.nty; ++t)
+            if (b->h_flags[P.full0 + t]) {
+                hp[n] = p;
+                ht[n] = t;
+                ++n;
+            }
+        if (n == P.item0) {
+            hp[n] = p;
+            ht[n] = 0;
+            ++n;
+        }
+        P.nt = n - P.item0;
+    }
+    b->nlive = n;
+    return upload_items(b);
+}
+
+bool all_assembled(const vfs_batch* b) {
+    for (auto* c : b->ctx)
+        if (!c->assembled) return false;
+    return true;
+}
+
+// (re)build the tile list of every problem for the current tile variant; the
+// live items are all tiles until the next assembly compacts them
 int build_items(vfs_batch* b) {
     int bx, by;
     batch_tile_shape(b->variant, &bx, &by);
-    std::vector<int> item_prob;
+    std::vector<int> full_prob;
     b->h_prob.assign(b->n, BProb{});
     for (int p = 0; p < b->n; ++p) {
         vfs_ctx* c = b->ctx[p];
@@ -101,9 +166,10 @@ int build_items(vfs_batch* b) {
         P.g = c->g;
         P.ntx = (c->g.nx + 1 + bx - 1) / bx;
         P.nty = (c->g.ny + 1 + by - 1) / by;
+        P.full0 = (int)full_prob.size();
+        P.item0 = P.full0;
         P.nt = P.ntx * P.nty;
-        P.item0 = (int)item_prob.size();
-        for (int t = 0; t < P.nt; ++t) item_prob.push_back(p);
+        for (int t = 0; t < P.nt; ++t) full_prob.push_back(p);
         P.x32 = c->x32;
         P.r32 = c->r32;
         P.p0 = c->p032;
@@ -122,23 +188,42 @@ int build_items(vfs_batch* b) {
         P.K64 = c->K;
         P.b64 = c->b;
     }
-    b->nitems = (int)item_prob.size();
-    if (b->d_item_prob) (void)hipFree(b->d_item_prob);
+    b->nfull = (int)full_prob.size();
+    int* dev[] = {b->d_item_prob, b->d_item_tile, b->d_nlive, b->d_full_prob, b->d_flags};
+    for (int* q : dev)
+        if (q) (void)hipFree(q);
     if (b->d_part) (void)hipFree(b->d_part);
-    b->d_item_prob = nullptr;
+    if (b->h_flags) (void)hipHostFree(b->h_flags);
+    b->d_item_prob = b->d_item_tile = b->d_nlive = b->d_full_prob = b->d_flags = nullptr;
     b->d_part = nullptr;
-    BCHK(hipMalloc((void**)&b->d_item_prob, sizeof(int) * b->nitems));
-    b->part_cap = (long long)b->nitems + 64;
+    b->h_flags = nullptr;
+    const size_t nf = sizeof(int) * b->nfull;
+    BCHK(hipMalloc((void**)&b->d_item_prob, nf));
+    BCHK(hipMalloc((void**)&b->d_item_tile, nf));
+    BCHK(hipMalloc((void**)&b->d_full_prob, nf));
+    BCHK(hipMalloc((void**)&b->d_flags, nf));
+    BCHK(hipMalloc((void**)&b->d_nlive, sizeof(int)));
+    BCHK(hipHostMalloc((void**)&b->h_flags, 3 * nf + sizeof(int), hipHostMallocDefault));
+    b->part_cap = (long long)b->nfull + 64;
     BCHK(hipMalloc((void**)&b->d_part, sizeof(double) * 11 * b->part_cap));
-    BCHK(hipMemcpy(b->d_item_prob, item_prob.data(), sizeof(int) * b->nitems,
-                   hipMemcpyHostToDevice));
-    BCHK(hipMemcpy(b->d_prob, b->h_prob.data(), sizeof(BProb) * b->n, hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(b->d_full_prob, full_prob.data(), nf, hipMemcpyHostToDevice));
+    int* hp = b->h_flags + b->nfull;
+    int* ht = hp + b->nfull;
+    for (int p = 0, n = 0; p < b->n; ++p)
+        for (int t = 0; t < b->h_prob[p].nt; ++t, ++n) {
+            hp[n] = p;
+            ht[n] = t;
+        }
+    b->nlive = b->nfull;
+    int rc = upload_items(b);
+    if (rc) return rc;
+    if (all_assembled(b) && (rc = compact_items(b))) return rc;
     int bpc = 0;
     if (batch_pcg_occupancy(b->variant, &bpc) != 0 || bpc < 1)
         return bfail(b, VFS_EHIP, "occupancy query failed");
     const int use = std::max(1, std::min(b->blocks_per_cu, bpc));
     b->bpc_used = use;
-    b->grid = std::max(1, std::min(b->ncu * use, b->nitems));
+    b->grid = std::max(1, std::min(b->ncu * use, b->nfull));
     if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
@@ -155,7 +240,7 @@ int build_items(vfs_batch* b) {
 // (inner FP32 CG, FP64 residual and refinement for every problem)
 void enqueue_solve(vfs_batch* b, hipStream_t s) {
     const BatchArgs A0 = args(b, 1);
-    launch_batch_zero_x(A0, b->grid, s);
+    launch_batch_zero(A0, s);
     launch_batch_resid(b->variant, A0, b->grid, s);
     launch_batch_finalize(A0, s);
     const BatchArgs A = args(b, 0);
@@ -229,9 +314,11 @@ int vfs_batch_destroy(vfs_batch* b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     for (auto* c : b->ctx) vfs_destroy(c);
-    void* bufs[] = {b->d_prob, b->d_state, b->d_ctl, b->d_item_prob, b->d_part};
+    void* bufs[] = {b->d_prob,      b->d_state,   b->d_ctl,   b->d_item_prob, b->d_item_tile,
+                    b->d_full_prob, b->d_flags,   b->d_nlive, b->d_part};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    if (b->h_flags) (void)hipHostFree(b->h_flags);
     if (b->h_state) (void)hipHostFree(b->h_state);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     for (auto& e : b->ev)
@@ -368,6 +455,8 @@ int vfs_batch_step(vfs_batch* b, double dt) {
         int rc = ctx_assemble(b->ctx[p], dt);
         if (rc) return bfail(b, rc, "problem " + std::to_string(p) + ": " + vfs_last_error(b->ctx[p]));
     }
+    int rc = compact_items(b);
+    if (rc) return rc;
     BCHK(hipEventRecord(b->ev[1], s));
     const int status = solve_all(b, true);
     if (status != VFS_OK && status != VFS_ENOTCONV) return status;
@@ -390,6 +479,12 @@ int vfs_batch_step(vfs_batch* b, double dt) {
     S.t_assemble_ms = ev_ms(b->ev[0], b->ev[1]);
     S.t_solve_ms = ev_ms(b->ev[1], b->ev[2]);
     S.t_step_ms = ev_ms(b->ev[0], b->ev[3]);
+    {
+        int bx, by;
+        batch_tile_shape(b->variant, &bx, &by);
+        S.n_items = b->nlive;
+        S.n_tile_samples = (int64_t)b->nlive * bx * by * 3;
+    }
     std::vector<double> lat;
     for (int p = 0; p < b->n; ++p) {
         const BState& st = b->h_state[p];
@@ -469,8 +564,7 @@ int vfs_batch_time_variant(vfs_batch* b, int variant, int blocks_per_cu, int ite
                            double* ms_per_iteration) {
     if (!b || !ms_per_iteration) return VFS_EINVAL;
     if (iterations < 1) return bfail(b, VFS_EINVAL, "iterations must be >= 1");
-    for (auto* c : b->ctx)
-        if (!c->assembled) return bfail(b, VFS_ESTATE, "run vfs_batch_step once before timing");
+    if (!all_assembled(b)) return bfail(b, VFS_ESTATE, "run vfs_batch_step once before timing");
     const int v0 = b->variant, c0 = b->blocks_per_cu;
     int rc = vfs_batch_set_tiles(b, variant, blocks_per_cu);
     if (rc) return rc;
@@ -479,7 +573,7 @@ int vfs_batch_time_variant(vfs_batch* b, int variant, int blocks_per_cu, int ite
     b->max_passes = 1;
     hipStream_t s = b->stream;
     const BatchArgs A0 = args(b, 1);
-    launch_batch_zero_x(A0, b->grid, s);
+    launch_batch_zero(A0, s);
     launch_batch_resid(b->variant, A0, b->grid, s);
     launch_batch_finalize(A0, s);
     const BatchArgs A = args(b, 0);

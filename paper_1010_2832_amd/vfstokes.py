@@ -53,7 +53,8 @@ class vfs_batch_stats(ctypes.Structure):
                 ("t_assemble_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("t_step_ms", ctypes.c_double), ("latency_p50_ms", ctypes.c_double),
                 ("latency_p90_ms", ctypes.c_double), ("latency_p99_ms", ctypes.c_double),
-                ("latency_max_ms", ctypes.c_double)]
+                ("latency_max_ms", ctypes.c_double), ("n_items", ctypes.c_int64),
+                ("n_tile_samples", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import cases
-from gpu_util import flat_faces, velocity_rel_linf
+from gpu_util import expected_tile_samples, flat_faces, velocity_rel_linf
 from oracle import system
 
 pytestmark = pytest.mark.gpu
@@ -39,6 +39,42 @@ def test_batch_matches_oracle_every_tile_variant(variant):
         assert pr["rel_residual"] <= 1e-9
         assert system.true_relative_residual(asm, b.vfs_batch_get_solution(i)) <= 2e-9
         assert err <= 1e-4, (i, err)
+    b.close()
+
+
+def test_batch_items_are_the_active_tiles():
+    """Work items are the tiles holding an active sample.  For every tile
+    shape their count equals the count of tiles over the oracle's active set,
+    an all-air problem keeps a single item and retires at once (its velocity
+    equals the oracle's), a 3x3 problem smaller than one tile solves, and the
+    others match the oracle.  Every step restarts from u^0."""
+    from paper_1010_2832_amd import vfstokes as V
+    probs = _problems([48, 64, 40, 3], seed=11)
+    air = cases.drop2d(32, 1105)
+    air["phi_l"] = np.ones_like(air["phi_l"])      # all air: no active sample
+    probs.insert(2, air)
+    ref = [system.step(c) for c in probs]
+    b = V.batch_from_cases(probs, tol=1e-9)
+    for variant in range(V.vfs_batch_num_variants()):
+        bx, by = V.vfs_batch_variant_shape(variant)
+        for i, c in enumerate(probs):
+            b.vfs_batch_set_problem(i, c)
+        b.vfs_batch_set_tiles(variant, 2)
+        b.vfs_batch_step(probs[0]["dt"])
+        st = b.vfs_batch_get_stats()
+        tiles = [expected_tile_samples(asm, (bx, by)) // (bx * by * 3) for asm, _, _ in ref]
+        want = sum(max(1, t) for t in tiles)
+        _banner(f"variant {variant} ({bx}x{by}): active tiles {tiles}, items {st['n_items']}")
+        assert st["status"] == 0
+        assert st["n_items"] == want and st["n_tile_samples"] == want * bx * by * 3
+        for i, (asm, x, u) in enumerate(ref):
+            ug = flat_faces(asm.grid, b.vfs_batch_get_velocity(i))
+            pr = b.vfs_batch_get_problem(i)
+            assert pr["n_active"] == int(asm.active.sum())
+            if pr["n_active"] == 0:
+                assert pr["iterations"] == 0 and np.array_equal(ug, u), i
+            else:
+                assert velocity_rel_linf(asm, ug, u) <= 1e-4, (variant, i)
     b.close()
 
 
