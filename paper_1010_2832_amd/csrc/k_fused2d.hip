@@ -55,9 +55,10 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
                                                 const T* __restrict__ a, const T* __restrict__ c,
                                                 const T* __restrict__ K, const int* __restrict__ tiles,
                                                 int ntx, RedArgs ra) {
-    constexpr int RPT = BY * BX / NT;
-    constexpr int NE1 = ((BX + 2) * (BY + 2) + NT - 1) / NT;
+    constexpr int RPT = BY * BX / NT;              // own anchors per thread
+    constexpr int NH = 2 * (BX + 2) + 2 * BY;      // halo ring of the tile
     constexpr int NE2 = ((BX + 1) * (BY + 1) + NT - 1) / NT;
+    static_assert(RPT * NT == BX * BY && NH <= NT, "tile shape");
     const int bid = blockIdx.x;
     Scalars* sc = ra.sc;
     const int k = ra.kidx;
@@ -69,42 +70,71 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     T* __restrict__ p_out = static_cast<T*>(v.p[pout]);
     T* __restrict__ q_out = static_cast<T*>(v.q[pout]);
     T* __restrict__ x = static_cast<T*>(v.x);
-    __shared__ T sV[3][BY + 2][BX + 2];   // p_k
-    __shared__ T sW[3][BY + 2][BX + 2];   // a p_k
-    __shared__ T sZ[3][BY + 2][BX + 2];   // z_k
-    __shared__ T sD[3][BY + 2][BX + 2];   // D^-1
+    __shared__ T sW[3][BY + 2][BX + 2];   // a p_k on the tile and its halo
     __shared__ T sG[2][BY + 1][BX + 1];
     const long long NP = g.NP;
     const int tile = tiles[xcd_tile(bid, gridDim.x)];
     const int i0 = (tile % ntx) * BX, j0 = (tile / ntx) * BY;
     const int tid = threadIdx.x;
+    // own anchors (i0 + tx, j0 + ty(rr)); the same thread forms p, z and q
+    // there, so only a p crosses threads (through LDS)
+    const int tx = tid % BX;
+    auto own_row = [&](int rr) { return tid / BX + rr * (NT / BX); };
+    // halo ring position of thread tid < NH: rows lj = 0 and BY + 1 (corners
+    // included), then columns li = 0 and BX + 1
+    const bool hrole = tid < NH;
+    int hli = 0, hlj = 0;
+    if (tid < BX + 2) {
+        hli = tid;
+    } else if (tid < 2 * (BX + 2)) {
+        hli = tid - (BX + 2);
+        hlj = BY + 1;
+    } else if (hrole) {
+        const int e = tid - 2 * (BX + 2);
+        hlj = 1 + (e >> 1);
+        hli = (e & 1) ? BX + 1 : 0;
+    }
 
     // (1) partials of the previous launch
     PartialLoads<NV, NT, 4> pl;
     if (!INIT) pl.load(ra.part_in, ra.nb_in);
 
-    // (2) loads that do not depend on the totals
-    T Rr[NE1][3], Dd[NE1][3], Qq[NE1][3], Pp[NE1][3], Aa[NE1][3], Xx[NE1][3];
-    bool in1[NE1], own1[NE1];
+    // (2) loads that do not depend on the totals.  Positions outside the grid
+    // read offset 0 of each slice, its zero pad, so no load is guarded.
+    T Rr[RPT][3], Dd[RPT][3], Qq[RPT][3], Pp[RPT][3], Aa[RPT][3], Xx[RPT][3], Co[RPT][2];
+    bool own[RPT];
 #pragma unroll
-    for (int m = 0; m < NE1; ++m) {
-        const int e = tid + m * NT;
-        const int li = e % (BX + 2), lj = e / (BX + 2);
-        const int i = i0 - 1 + li, j = j0 - 1 + lj;
-        in1[m] = e < (BX + 2) * (BY + 2) && i <= g.nx + 1 && j <= g.ny + 1;
-        own1[m] = in1[m] && li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
-        // positions outside the grid read offset 0 of each slice, its zero pad
-        const long long o = in1[m] ? g.idx(i, j) : 0;
-        const long long ox = own1[m] ? o : 0;
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + tx, j = j0 + own_row(rr);
+        own[rr] = i <= g.nx && j <= g.ny;
+        const long long o = (i <= g.nx + 1 && j <= g.ny + 1) ? g.idx(i, j) : 0;
+        const long long ox = own[rr] ? o : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const long long os = o + s * NP;
-            Rr[m][s] = r_in[os];
-            Dd[m][s] = dinv[os];
-            Aa[m][s] = a[os];
-            Qq[m][s] = INIT ? T(0) : q_in[os];
-            Pp[m][s] = INIT ? T(0) : p_in[os];
-            Xx[m][s] = INIT ? T(0) : x[ox + s * NP];
+            Rr[rr][s] = r_in[os];
+            Dd[rr][s] = dinv[os];
+            Aa[rr][s] = a[os];
+            Qq[rr][s] = INIT ? T(0) : q_in[os];
+            Pp[rr][s] = INIT ? T(0) : p_in[os];
+            Xx[rr][s] = INIT ? T(0) : x[ox + s * NP];
+        }
+        Co[rr][0] = c[NP + ox];
+        Co[rr][1] = c[2 * NP + ox];
+    }
+    // halo loads only in the waves that hold halo positions
+    T Rh[3] = {}, Dh[3] = {}, Qh[3] = {}, Ph[3] = {}, Ah[3] = {};
+    if (hrole) {
+        const int i = i0 - 1 + hli, j = j0 - 1 + hlj;
+        const long long o = (i <= g.nx + 1 && j <= g.ny + 1) ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const long long os = o + s * NP;
+            Rh[s] = r_in[os];
+            Dh[s] = dinv[os];
+            Ah[s] = a[os];
+            Qh[s] = INIT ? T(0) : q_in[os];
+            Ph[s] = INIT ? T(0) : p_in[os];
         }
     }
     T Ku[NE2], Kv[NE2];
@@ -119,19 +149,6 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
         const bool okV = fe && iv >= 0 && iv < g.nx && jv <= g.ny;
         Ku[m] = K[okU ? g.idx(iu, ju) : 0];
         Kv[m] = K[NP + (okV ? g.idx(iv, jv) : 0)];
-    }
-    const int tx = tid % BX;
-    T Ao[RPT][3], Co[RPT][2];
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-        const int ty = tid / BX + rr * (NT / BX);
-        const int i = i0 + tx, j = j0 + ty;
-        const bool ok = i <= g.nx && j <= g.ny;
-        const long long o = ok ? g.idx(i, j) : 0;
-#pragma unroll
-        for (int s = 0; s < 3; ++s) Ao[rr][s] = a[o + s * NP];
-        Co[rr][0] = c[NP + o];
-        Co[rr][1] = c[2 * NP + o];
     }
 
     // (3) totals of iteration k-1 -> stop decision, alpha_{k-1}, beta_k.  The
@@ -176,32 +193,37 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
 
     // (4) tile and halo: r_k, z_k, p_k; own anchors also x_k
     double rz_n = 0.0, rr_n = 0.0;
+    T Vo[RPT][3], Zo[RPT][3];
 #pragma unroll
-    for (int m = 0; m < NE1; ++m) {
-        const int e = tid + m * NT;
-        if (e >= (BX + 2) * (BY + 2)) continue;
-        const int li = e % (BX + 2), lj = e / (BX + 2);
-        const int i = i0 - 1 + li, j = j0 - 1 + lj;
-        const long long o = in1[m] ? g.idx(i, j) : 0;
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int ty = own_row(rr);
+        const long long o = own[rr] ? g.idx(i0 + tx, j0 + ty) : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const T rn = INIT ? Rr[m][s] : Rr[m][s] - alpha * Qq[m][s];
-            const T zn = Dd[m][s] * rn;
-            const T pn = INIT ? zn : zn + beta * Pp[m][s];
-            if (own1[m]) {
+            const T rn = INIT ? Rr[rr][s] : Rr[rr][s] - alpha * Qq[rr][s];
+            const T zn = Dd[rr][s] * rn;
+            const T pn = INIT ? zn : zn + beta * Pp[rr][s];
+            if (own[rr]) {
                 const long long os = o + s * NP;
                 if (!INIT) {
                     r_out[os] = rn;
-                    x[os] = Xx[m][s] + alpha * Pp[m][s];
+                    x[os] = Xx[rr][s] + alpha * Pp[rr][s];
                 }
                 p_out[os] = pn;
                 rz_n += (double)rn * (double)zn;
                 rr_n += (double)rn * (double)rn;
             }
-            sV[s][lj][li] = pn;
-            sW[s][lj][li] = Aa[m][s] * pn;
-            sZ[s][lj][li] = zn;
-            sD[s][lj][li] = Dd[m][s];
+            Vo[rr][s] = pn;
+            Zo[rr][s] = zn;
+            sW[s][ty + 1][tx + 1] = Aa[rr][s] * pn;
+        }
+    }
+    if (hrole) {
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const T rn = INIT ? Rh[s] : Rh[s] - alpha * Qh[s];
+            const T pn = INIT ? Dh[s] * rn : Dh[s] * rn + beta * Ph[s];
+            sW[s][hlj][hli] = Ah[s] * pn;
         }
     }
     __syncthreads();
@@ -225,23 +247,22 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     double pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
-        const int ty = tid / BX + rr * (NT / BX);
-        const int i = i0 + tx, j = j0 + ty;
-        if (i <= g.nx && j <= g.ny) {
-            const long long o = g.idx(i, j);
+        const int ty = own_row(rr);
+        if (own[rr]) {
+            const long long o = g.idx(i0 + tx, j0 + ty);
             const T gu0 = sG[0][ty + 1][tx], gu1 = sG[0][ty + 1][tx + 1], gum = sG[0][ty][tx];
             const T gv0 = sG[1][ty][tx + 1], gv1 = sG[1][ty + 1][tx + 1], gvm = sG[1][ty][tx];
             T y[3];
-            y[0] = Ao[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
-            y[1] = Ao[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * sV[1][ty + 1][tx + 1];
-            y[2] = Ao[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * sV[2][ty + 1][tx + 1];
+            y[0] = Aa[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
+            y[1] = Aa[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * Vo[rr][1];
+            y[2] = Aa[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * Vo[rr][2];
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 q_out[o + s * NP] = y[s];
                 const double yd = y[s];
-                pq_n += (double)sV[s][ty + 1][tx + 1] * yd;
-                qz_n += (double)sZ[s][ty + 1][tx + 1] * yd;
-                qdq_n += (double)sD[s][ty + 1][tx + 1] * yd * yd;
+                pq_n += (double)Vo[rr][s] * yd;
+                qz_n += (double)Zo[rr][s] * yd;
+                qdq_n += (double)Dd[rr][s] * yd * yd;
             }
         }
     }
