@@ -236,8 +236,9 @@ template <int BX, int BY, bool INIT>
 __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float beta, int k,
                            float* lds, double (&v)[5]) {
     constexpr int HX = BX + 2, HY = BY + 2, FX = BX + 1, FY = BY + 1;
-    constexpr int RPT = BY * BX / NT;
-    constexpr int NE1 = (HX * HY + NT - 1) / NT;
+    constexpr int RPT = BY * BX / NT;             // own anchors per thread
+    constexpr int NH = 2 * HX + 2 * BY;           // halo ring of the tile
+    constexpr int NHR = (NH + NT - 1) / NT;
     constexpr int NE2 = (FX * FY + NT - 1) / NT;
     static_assert(RPT * NT == BX * BY && NT % BX == 0, "tile must be a multiple of the workgroup");
     const Geo& g = P.g;
@@ -256,39 +257,77 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
     const float* __restrict__ a = P.a;
     const float* __restrict__ c = P.c;
     const float* __restrict__ K = P.K;
-    float* sV = lds;                     // p        [3][HY][HX]
-    float* sW = sV + 3 * HY * HX;        // a p
-    float* sZ = sW + 3 * HY * HX;        // z
-    float* sD = sZ + 3 * HY * HX;        // D^-1
-    float* sG = sD + 3 * HY * HX;        // faces    [2][FY][FX]
+    float* sW = lds;                     // a p      [3][HY][HX]
+    float* sG = sW + 3 * HY * HX;        // faces    [2][FY][FX]
     const long long NP = g.NP;
     const int tid = threadIdx.x;
+    const int tx = tid % BX;
 #define L3(arr, s_, y_, x_) arr[((s_) * HY + (y_)) * HX + (x_)]
 #define G2(f_, y_, x_) sG[((f_) * FY + (y_)) * FX + (x_)]
-    float Rr[NE1][3], Dd[NE1][3], Qq[NE1][3], Pp[NE1][3], Aa[NE1][3], Xx[NE1][3];
-    bool in1[NE1], own1[NE1];
+    // own anchors (i0 + tx, j0 + ty): the thread that forms p, z there also
+    // forms q there, so only a p crosses threads (through LDS)
+    float Rr[RPT][3], Dd[RPT][3], Qq[RPT][3], Pp[RPT][3], Aa[RPT][3], Xx[RPT][3], Co[RPT][2];
+    bool own[RPT];
 #pragma unroll
-    for (int m = 0; m < NE1; ++m) {
-        const int e = tid + m * NT;
-        const int li = e % HX, lj = e / HX;
-        const int i = i0 - 1 + li, j = j0 - 1 + lj;
-        in1[m] = e < HX * HY && i <= g.nx + 1 && j <= g.ny + 1;
-        own1[m] = in1[m] && li >= 1 && li <= BX && lj >= 1 && lj <= BY && i <= g.nx && j <= g.ny;
-        const long long o = in1[m] ? g.idx(i, j) : 0;
+    for (int rr = 0; rr < RPT; ++rr) {
+        const int i = i0 + tx, j = j0 + tid / BX + rr * (NT / BX);
+        const bool in = i <= g.nx + 1 && j <= g.ny + 1;
+        own[rr] = i <= g.nx && j <= g.ny;
+        const long long o = in ? g.idx(i, j) : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const long long os = o + s * NP;
-            Rr[m][s] = Dd[m][s] = Qq[m][s] = Pp[m][s] = Aa[m][s] = Xx[m][s] = 0.f;
-            if (in1[m]) {
-                Rr[m][s] = r_in[os];
-                Dd[m][s] = dinv[os];
-                Aa[m][s] = a[os];
+            Rr[rr][s] = Dd[rr][s] = Qq[rr][s] = Pp[rr][s] = Aa[rr][s] = Xx[rr][s] = 0.f;
+            if (in) {
+                Rr[rr][s] = r_in[os];
+                Dd[rr][s] = dinv[os];
+                Aa[rr][s] = a[os];
                 if (!INIT) {
-                    Qq[m][s] = q_in[os];
-                    Pp[m][s] = p_in[os];
+                    Qq[rr][s] = q_in[os];
+                    Pp[rr][s] = p_in[os];
                 }
             }
-            if (!INIT && own1[m]) Xx[m][s] = x[os];
+            if (!INIT && own[rr]) Xx[rr][s] = x[os];
+        }
+        Co[rr][0] = own[rr] ? c[NP + o] : 0.f;
+        Co[rr][1] = own[rr] ? c[2 * NP + o] : 0.f;
+    }
+    // halo ring: rows lj = 0 and HY - 1 (corners included), then columns
+    // li = 0 and HX - 1; position h = tid + m NT
+    float Rh[NHR][3], Dh[NHR][3], Qh[NHR][3], Ph[NHR][3], Ah[NHR][3];
+    int hli[NHR], hlj[NHR];
+#pragma unroll
+    for (int m = 0; m < NHR; ++m) {
+        const int h = tid + m * NT;
+        int li = 0, lj = 0;
+        if (h < HX) {
+            li = h;
+        } else if (h < 2 * HX) {
+            li = h - HX;
+            lj = HY - 1;
+        } else {
+            const int e = h - 2 * HX;
+            lj = 1 + (e >> 1);
+            li = (e & 1) ? HX - 1 : 0;
+        }
+        hli[m] = li;
+        hlj[m] = lj;
+        const int i = i0 - 1 + li, j = j0 - 1 + lj;
+        const bool in = h < NH && i <= g.nx + 1 && j <= g.ny + 1;
+        const long long o = in ? g.idx(i, j) : 0;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const long long os = o + s * NP;
+            Rh[m][s] = Dh[m][s] = Qh[m][s] = Ph[m][s] = Ah[m][s] = 0.f;
+            if (in) {
+                Rh[m][s] = r_in[os];
+                Dh[m][s] = dinv[os];
+                Ah[m][s] = a[os];
+                if (!INIT) {
+                    Qh[m][s] = q_in[os];
+                    Ph[m][s] = p_in[os];
+                }
+            }
         }
     }
     float Ku[NE2], Kv[NE2];
@@ -304,45 +343,40 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
             if (iv >= 0 && iv < g.nx && jv <= g.ny) Kv[m] = K[NP + g.idx(iv, jv)];
         }
     }
-    const int tx = tid % BX;
-    float Ao[RPT][3], Co[RPT][2];
+    // r_k, z_k, p_k on the tile and its halo; own anchors also store r, x, p
+    float Vo[RPT][3], Zo[RPT][3];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int ty = tid / BX + rr * (NT / BX);
-        const int i = i0 + tx, j = j0 + ty;
-        const bool ok = i <= g.nx && j <= g.ny;
-        const long long o = ok ? g.idx(i, j) : 0;
-#pragma unroll
-        for (int s = 0; s < 3; ++s) Ao[rr][s] = ok ? a[o + s * NP] : 0.f;
-        Co[rr][0] = ok ? c[NP + o] : 0.f;
-        Co[rr][1] = ok ? c[2 * NP + o] : 0.f;
-    }
-#pragma unroll
-    for (int m = 0; m < NE1; ++m) {
-        const int e = tid + m * NT;
-        if (e >= HX * HY) continue;
-        const int li = e % HX, lj = e / HX;
-        const int i = i0 - 1 + li, j = j0 - 1 + lj;
-        const long long o = in1[m] ? g.idx(i, j) : 0;
+        const long long o = own[rr] ? g.idx(i0 + tx, j0 + ty) : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const float rn = INIT ? Rr[m][s] : Rr[m][s] - alpha * Qq[m][s];
-            const float zn = Dd[m][s] * rn;
-            const float pn = INIT ? zn : zn + beta * Pp[m][s];
-            if (own1[m]) {
+            const float rn = INIT ? Rr[rr][s] : Rr[rr][s] - alpha * Qq[rr][s];
+            const float zn = Dd[rr][s] * rn;
+            const float pn = INIT ? zn : zn + beta * Pp[rr][s];
+            if (own[rr]) {
                 const long long os = o + s * NP;
                 if (!INIT) {
                     r_out[os] = rn;
-                    x[os] = Xx[m][s] + alpha * Pp[m][s];
+                    x[os] = Xx[rr][s] + alpha * Pp[rr][s];
                 }
                 p_out[os] = pn;
                 v[0] += (double)rn * (double)zn;
                 v[4] += (double)rn * (double)rn;
             }
-            L3(sV, s, lj, li) = pn;
-            L3(sW, s, lj, li) = Aa[m][s] * pn;
-            L3(sZ, s, lj, li) = zn;
-            L3(sD, s, lj, li) = Dd[m][s];
+            Vo[rr][s] = pn;
+            Zo[rr][s] = zn;
+            L3(sW, s, ty + 1, tx + 1) = Aa[rr][s] * pn;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NHR; ++m) {
+        if (tid + m * NT >= NH) continue;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const float rn = INIT ? Rh[m][s] : Rh[m][s] - alpha * Qh[m][s];
+            const float pn = INIT ? Dh[m][s] * rn : Dh[m][s] * rn + beta * Ph[m][s];
+            L3(sW, s, hlj[m], hli[m]) = Ah[m][s] * pn;
         }
     }
     __syncthreads();
@@ -362,22 +396,21 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int ty = tid / BX + rr * (NT / BX);
-        const int i = i0 + tx, j = j0 + ty;
-        if (i <= g.nx && j <= g.ny) {
-            const long long o = g.idx(i, j);
+        if (own[rr]) {
+            const long long o = g.idx(i0 + tx, j0 + ty);
             const float gu0 = G2(0, ty + 1, tx), gu1 = G2(0, ty + 1, tx + 1), gum = G2(0, ty, tx);
             const float gv0 = G2(1, ty, tx + 1), gv1 = G2(1, ty + 1, tx + 1), gvm = G2(1, ty, tx);
             float y[3];
-            y[0] = Ao[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
-            y[1] = Ao[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * L3(sV, 1, ty + 1, tx + 1);
-            y[2] = Ao[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * L3(sV, 2, ty + 1, tx + 1);
+            y[0] = Aa[rr][0] * ((gu0 - gu1) + (gv0 - gv1));
+            y[1] = Aa[rr][1] * ((gu1 - gu0) + (gv0 - gv1)) + Co[rr][0] * Vo[rr][1];
+            y[2] = Aa[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * Vo[rr][2];
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 q_out[o + s * NP] = y[s];
                 const double yd = y[s];
-                v[1] += (double)L3(sV, s, ty + 1, tx + 1) * yd;
-                v[2] += (double)L3(sZ, s, ty + 1, tx + 1) * yd;
-                v[3] += (double)L3(sD, s, ty + 1, tx + 1) * yd * yd;
+                v[1] += (double)Vo[rr][s] * yd;
+                v[2] += (double)Zo[rr][s] * yd;
+                v[3] += (double)Dd[rr][s] * yd * yd;
             }
         }
     }
