@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
-    ap.add_argument("--cpu-iters", type=int, default=400)
+    ap.add_argument("--cpu-iters", type=int, default=3000)
     ap.add_argument("--no-config3", action="store_true",
                     help="skip the 128^3 FP64-vs-mixed leg")
     ap.add_argument("--no-config4", action="store_true",
