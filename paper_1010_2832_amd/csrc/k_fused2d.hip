@@ -33,7 +33,7 @@
 namespace vfs {
 namespace {
 
-constexpr int NT = 512;
+constexpr int NT = 384;
 constexpr int NV = 5;   // r.z, p.q, q.D^-1 r, q.D^-1 q, r.r
 
 // Tile of workgroup b (one tile per workgroup).  Workgroups are dispatched
@@ -95,8 +95,9 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
         hli = (e & 1) ? BX + 1 : 0;
     }
 
-    // (1) partials of the previous launch
-    PartialLoads<NV, NT, 4> pl;
+    // (1) partials of the previous launch (one per thread in registers; a
+    // longer list is finished by a loop)
+    PartialLoads<NV, NT, 1> pl;
     if (!INIT) pl.load(ra.part_in, ra.nb_in);
 
     // (2) loads that do not depend on the totals.  Positions outside the grid
@@ -312,10 +313,12 @@ __global__ __launch_bounds__(1024) void k_tiles2d_compact(int n, const int* __re
         if (flags[t]) list[w++] = t;
 }
 
-// tile shape and workgroup size: 64 x 16 anchors with 512 threads was the
-// fastest of ten shapes and sizes on the 512^2 workload with the XCD map
-// (399.0 ms per solve against 415.7 for 64 x 8 with 256 threads)
-constexpr int kBX = 64, kBY = 16;
+// tile shape and workgroup size: 64 x 12 anchors with 384 threads (two own
+// anchors per thread) was the fastest of the shapes swept on the 512^2
+// workload: about one tile per compute unit (310.4 ms per solve against 318.1
+// for 64 x 16 with 512 threads, 316.6 for 64 x 14, 325.1 for 64 x 12 with 256
+// threads)
+constexpr int kBX = 64, kBY = 12;
 
 }  // namespace
 

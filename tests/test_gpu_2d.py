@@ -115,8 +115,8 @@ def test_step_mixed_matches_oracle(name):
     _banner(f"  iters {st['iterations']} outer {st['outer_iterations']} rel_res {st['rel_residual']:.2e} vel err {err:.2e}")
     assert st["rel_residual"] <= 1e-9
     assert err <= 1e-4
-    # the active-tile list covers exactly the 64x16 tiles holding an active sample
-    assert st["n_tile_samples"] == expected_tile_samples(asm, (64, 16))
+    # the active-tile list covers exactly the 64x12 tiles holding an active sample
+    assert st["n_tile_samples"] == expected_tile_samples(asm, (64, 12))
 
 
 def test_config2_full_size_mixed():
