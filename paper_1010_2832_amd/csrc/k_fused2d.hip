@@ -47,13 +47,58 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return x * q + min(x, rem) + slot;
 }
 
+// Base address of every slice the launch reads or writes, passed as kernel
+// arguments (the parity buffers are picked on the host).  Each load or store
+// then takes its base in scalar registers and one 32-bit byte offset per lane,
+// shared by every slice read at that position, instead of a 64-bit address
+// per lane and access (slice bases computed inside the kernel get folded into
+// the per-lane addresses).  Offsets stay within one slice (at most about
+// 2.7e8 elements for the largest 2D grid, 16384^2), far below 4 GiB.
+template <typename T>
+struct Slices2d {
+    const T* r[3];   // r_{k-1} (launch 0: r_0)
+    const T* q[3];   // q_{k-1}
+    const T* p[3];   // p_{k-1}
+    const T* d[3];   // D^-1
+    const T* a[3];   // sample weights
+    T* x[3];         // x, read and written in place
+    const T* c[2];   // diagonal coefficients of slices 1 and 2
+    const T* K[2];   // face coefficients (u, v)
+    T* ro[3];        // r_k
+    T* po[3];        // p_k
+    T* qo[3];        // q_k
+};
+
+// Byte offset of anchor (i, j) in a slice, or 0 (the slice's zero pad) when
+// ok is false; computed in 32 bits with a mask rather than a select (which
+// the compiler turns into a branch), so that every load sees a zero-extended
+// 32-bit offset.
+template <typename T>
+__device__ __forceinline__ unsigned boff2d(const Geo& g, int i, int j, bool ok) {
+    const unsigned e = (unsigned)kFront + (unsigned)(j + 1) * (unsigned)g.PX + (unsigned)i;
+    unsigned b = (e * (unsigned)sizeof(T)) & (0u - (unsigned)ok);
+    // opaque to the optimizer (no instruction is emitted; not volatile, so it
+    // does not pin the schedule): it would otherwise widen the mask to 64
+    // bits and the loads would lose the 32-bit offset form
+    asm("" : "+v"(b));
+    return b;
+}
+
+// Element at byte offset boff of a slice.
+template <typename T>
+__device__ __forceinline__ T ldo(const T* __restrict__ base, unsigned boff) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T* __restrict__ base, unsigned boff, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
 // Launched over the compacted list of tiles that hold an active sample;
 // the vectors of the other tiles stay zero (they hold no active sample), so
 // their values read as halo are correct.
 template <typename T, bool INIT, int BX, int BY>
-__global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __restrict__ dinv,
-                                                const T* __restrict__ a, const T* __restrict__ c,
-                                                const T* __restrict__ K, const int* __restrict__ tiles,
+__global__ __launch_bounds__(NT) void k_fused2d(Geo g, Slices2d<T> S, const int* __restrict__ tiles,
                                                 int ntx, RedArgs ra) {
     constexpr int RPT = BY * BX / NT;              // own anchors per thread
     constexpr int NH = 2 * (BX + 2) + 2 * BY;      // halo ring of the tile
@@ -62,17 +107,8 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     const int bid = blockIdx.x;
     Scalars* sc = ra.sc;
     const int k = ra.kidx;
-    const int pin = (k + 1) & 1, pout = k & 1;   // launch k reads slot (k-1)&1, writes k&1
-    const T* __restrict__ r_in = static_cast<const T*>(v.r[INIT ? 0 : pin]);
-    const T* __restrict__ q_in = static_cast<const T*>(v.q[pin]);
-    const T* __restrict__ p_in = static_cast<const T*>(v.p[pin]);
-    T* __restrict__ r_out = static_cast<T*>(v.r[pout]);
-    T* __restrict__ p_out = static_cast<T*>(v.p[pout]);
-    T* __restrict__ q_out = static_cast<T*>(v.q[pout]);
-    T* __restrict__ x = static_cast<T*>(v.x);
     __shared__ T sW[3][BY + 2][BX + 2];   // a p_k on the tile and its halo
     __shared__ T sG[2][BY + 1][BX + 1];
-    const long long NP = g.NP;
     const int tile = tiles[xcd_tile(bid, gridDim.x)];
     const int i0 = (tile % ntx) * BX, j0 = (tile / ntx) * BY;
     const int tid = threadIdx.x;
@@ -104,38 +140,39 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     // read offset 0 of each slice, its zero pad, so no load is guarded.
     T Rr[RPT][3], Dd[RPT][3], Qq[RPT][3], Pp[RPT][3], Aa[RPT][3], Xx[RPT][3], Co[RPT][2];
     bool own[RPT];
+    unsigned Ob[RPT];   // byte offset of the own anchor in a slice (0 outside the grid)
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int i = i0 + tx, j = j0 + own_row(rr);
         own[rr] = i <= g.nx && j <= g.ny;
-        const long long o = (i <= g.nx + 1 && j <= g.ny + 1) ? g.idx(i, j) : 0;
-        const long long ox = own[rr] ? o : 0;
+        const unsigned ob = boff2d<T>(g, i, j, i <= g.nx + 1 && j <= g.ny + 1);
+        unsigned oxb = ob & (0u - (unsigned)own[rr]);
+        asm("" : "+v"(oxb));   // keeps the 32-bit offset form (see boff2d)
+        Ob[rr] = oxb;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const long long os = o + s * NP;
-            Rr[rr][s] = r_in[os];
-            Dd[rr][s] = dinv[os];
-            Aa[rr][s] = a[os];
-            Qq[rr][s] = INIT ? T(0) : q_in[os];
-            Pp[rr][s] = INIT ? T(0) : p_in[os];
-            Xx[rr][s] = INIT ? T(0) : x[ox + s * NP];
+            Rr[rr][s] = ldo(S.r[s], ob);
+            Dd[rr][s] = ldo(S.d[s], ob);
+            Aa[rr][s] = ldo(S.a[s], ob);
+            Qq[rr][s] = INIT ? T(0) : ldo(S.q[s], ob);
+            Pp[rr][s] = INIT ? T(0) : ldo(S.p[s], ob);
+            Xx[rr][s] = INIT ? T(0) : ldo<T>(S.x[s], oxb);
         }
-        Co[rr][0] = c[NP + ox];
-        Co[rr][1] = c[2 * NP + ox];
+        Co[rr][0] = ldo(S.c[0], oxb);
+        Co[rr][1] = ldo(S.c[1], oxb);
     }
     // halo loads only in the waves that hold halo positions
     T Rh[3] = {}, Dh[3] = {}, Qh[3] = {}, Ph[3] = {}, Ah[3] = {};
     if (hrole) {
         const int i = i0 - 1 + hli, j = j0 - 1 + hlj;
-        const long long o = (i <= g.nx + 1 && j <= g.ny + 1) ? g.idx(i, j) : 0;
+        const unsigned ob = boff2d<T>(g, i, j, i <= g.nx + 1 && j <= g.ny + 1);
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const long long os = o + s * NP;
-            Rh[s] = r_in[os];
-            Dh[s] = dinv[os];
-            Ah[s] = a[os];
-            Qh[s] = INIT ? T(0) : q_in[os];
-            Ph[s] = INIT ? T(0) : p_in[os];
+            Rh[s] = ldo(S.r[s], ob);
+            Dh[s] = ldo(S.d[s], ob);
+            Ah[s] = ldo(S.a[s], ob);
+            Qh[s] = INIT ? T(0) : ldo(S.q[s], ob);
+            Ph[s] = INIT ? T(0) : ldo(S.p[s], ob);
         }
     }
     T Ku[NE2], Kv[NE2];
@@ -148,8 +185,8 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
         const int iv = i0 - 1 + li, jv = j0 + lj;
         const bool okU = fe && iu <= g.nx && ju >= 0 && ju < g.ny;
         const bool okV = fe && iv >= 0 && iv < g.nx && jv <= g.ny;
-        Ku[m] = K[okU ? g.idx(iu, ju) : 0];
-        Kv[m] = K[NP + (okV ? g.idx(iv, jv) : 0)];
+        Ku[m] = ldo(S.K[0], boff2d<T>(g, iu, ju, okU));
+        Kv[m] = ldo(S.K[1], boff2d<T>(g, iv, jv, okV));
     }
 
     // (3) totals of iteration k-1 -> stop decision, alpha_{k-1}, beta_k.  The
@@ -198,19 +235,19 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int ty = own_row(rr);
-        const long long o = own[rr] ? g.idx(i0 + tx, j0 + ty) : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const T rn = INIT ? Rr[rr][s] : Rr[rr][s] - alpha * Qq[rr][s];
             const T zn = Dd[rr][s] * rn;
             const T pn = INIT ? zn : zn + beta * Pp[rr][s];
             if (own[rr]) {
-                const long long os = o + s * NP;
+                unsigned ob = Ob[rr];
+                asm("" : "+v"(ob));   // 32-bit offset form in this block too
                 if (!INIT) {
-                    r_out[os] = rn;
-                    x[os] = Xx[rr][s] + alpha * Pp[rr][s];
+                    sto(S.ro[s], ob, rn);
+                    sto(S.x[s], ob, Xx[rr][s] + alpha * Pp[rr][s]);
                 }
-                p_out[os] = pn;
+                sto(S.po[s], ob, pn);
                 rz_n += (double)rn * (double)zn;
                 rr_n += (double)rn * (double)rn;
             }
@@ -250,7 +287,8 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
     for (int rr = 0; rr < RPT; ++rr) {
         const int ty = own_row(rr);
         if (own[rr]) {
-            const long long o = g.idx(i0 + tx, j0 + ty);
+            unsigned ob = Ob[rr];
+            asm("" : "+v"(ob));
             const T gu0 = sG[0][ty + 1][tx], gu1 = sG[0][ty + 1][tx + 1], gum = sG[0][ty][tx];
             const T gv0 = sG[1][ty][tx + 1], gv1 = sG[1][ty + 1][tx + 1], gvm = sG[1][ty][tx];
             T y[3];
@@ -259,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_fused2d(Geo g, FusedVecs v, const T* __r
             y[2] = Aa[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * Vo[rr][2];
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                q_out[o + s * NP] = y[s];
+                sto(S.qo[s], ob, y[s]);
                 const double yd = y[s];
                 pq_n += (double)Vo[rr][s] * yd;
                 qz_n += (double)Zo[rr][s] * yd;
@@ -345,12 +383,31 @@ void launch_fused2d(const Geo& g, bool init, const FusedVecs& v, const T* dinv, 
     if (count <= 0) return;
     int ntx, nty;
     fused2d_tile_dims(g, ntx, nty);
+    // launch k reads the slot (k-1)&1 of r, p, q and writes slot k&1
+    const int pin = (ra.kidx + 1) & 1, pout = ra.kidx & 1;
+    const long long NP = g.NP;
+    Slices2d<T> S{};
+    for (int q = 0; q < 3; ++q) {
+        S.r[q] = static_cast<const T*>(v.r[init ? 0 : pin]) + q * NP;
+        S.q[q] = static_cast<const T*>(v.q[pin]) + q * NP;
+        S.p[q] = static_cast<const T*>(v.p[pin]) + q * NP;
+        S.d[q] = dinv + q * NP;
+        S.a[q] = a + q * NP;
+        S.x[q] = static_cast<T*>(v.x) + q * NP;
+        S.ro[q] = static_cast<T*>(v.r[pout]) + q * NP;
+        S.po[q] = static_cast<T*>(v.p[pout]) + q * NP;
+        S.qo[q] = static_cast<T*>(v.q[pout]) + q * NP;
+    }
+    S.c[0] = c + NP;
+    S.c[1] = c + 2 * NP;
+    S.K[0] = K;
+    S.K[1] = K + NP;
     if (init)
-        hipLaunchKernelGGL((k_fused2d<T, true, kBX, kBY>), dim3(count), dim3(NT), 0, s, g, v, dinv,
-                           a, c, K, tiles, ntx, ra);
+        hipLaunchKernelGGL((k_fused2d<T, true, kBX, kBY>), dim3(count), dim3(NT), 0, s, g, S, tiles,
+                           ntx, ra);
     else
-        hipLaunchKernelGGL((k_fused2d<T, false, kBX, kBY>), dim3(count), dim3(NT), 0, s, g, v, dinv,
-                           a, c, K, tiles, ntx, ra);
+        hipLaunchKernelGGL((k_fused2d<T, false, kBX, kBY>), dim3(count), dim3(NT), 0, s, g, S, tiles,
+                           ntx, ra);
 }
 
 template void launch_fused2d<float>(const Geo&, bool, const FusedVecs&, const float*, const float*,
