@@ -98,12 +98,12 @@ def cpu_baseline(case, iters, seconds_cap=30.0):
 WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96.npy")
 
 
-def config3_leg(V):
+def column128_leg(V):
     """FP64 plain PCG against mixed PCG with iterative refinement on the 3D
     128^3 column configuration, both to a 1e-6 FP64 relative residual."""
     import numpy as np
     import cases
-    case = cases.config3()
+    case = cases.column128()
     out = {"workload": "3D 128^3 column (radius 0.05, top 0.8) on a solid floor, mu 50, rho 1, "
                        "u = (0,-0.5,0), g (0,-9.8,0), dt 1e-3, seed 3, both to 1e-6"}
     vel = {}
@@ -126,7 +126,7 @@ def config3_leg(V):
     return out
 
 
-def config4_leg(V, check=True):
+def batch64_leg(V, check=True):
     """Many uneven 2D solves in one persistent, graph-captured launch: the 64
     problems of sizes {64, 96, ..., 512}^2, tile shape and workgroups per CU
     picked by the autotuner, mixed precision to 1e-6.  Reports the solve time,
@@ -135,7 +135,7 @@ def config4_leg(V, check=True):
     import numpy as np
     import cases
     from paper_1010_2832_amd import autotune
-    probs = cases.config4()
+    probs = cases.batch64()
     sizes = [c["n"][0] for c in probs]
     b = V.batch_from_cases(probs, tol=1e-6)
     b.vfs_batch_step(probs[0]["dt"])          # first step: warms the code paths up
@@ -174,13 +174,13 @@ def config4_leg(V, check=True):
     return out
 
 
-def config5_leg(V, learned_cap=400):
+def pool256_leg(V, learned_cap=400):
     """Learned vs plain PCG on the 3D 256^3 configuration: Jacobi PCG in mixed
     precision to 1e-6, then truncated flexible CG with the committed network
     (capped at learned_cap iterations to bound the run) on the same step."""
     import numpy as np
     import cases
-    case = cases.config5()
+    case = cases.pool256()
     ctx = V.context_from_case(case, precision=V.VFS_MIXED, tol=1e-6)
     out = {"workload": "3D 256^3 pool (depth 0.3) + 8 spheres + moving solid sphere, mu log-uniform "
                        "[1,1000] smooth, rho [0.5,2], g (0,-9.8,0), dt 1e-3, seed 5, mixed to 1e-6"}
@@ -227,17 +227,17 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the oracle comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
     ap.add_argument("--cpu-iters", type=int, default=3000)
-    ap.add_argument("--no-config3", action="store_true",
+    ap.add_argument("--no-column128", action="store_true",
                     help="skip the 128^3 FP64-vs-mixed leg")
-    ap.add_argument("--no-config4", action="store_true",
+    ap.add_argument("--no-batch64", action="store_true",
                     help="skip the batched 64-problem 2D leg")
-    ap.add_argument("--no-config5", action="store_true",
+    ap.add_argument("--no-pool256", action="store_true",
                     help="skip the 256^3 learned-vs-plain leg")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: this library has no multi-GPU path.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -249,7 +249,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    case = cases.config2(seed=args.seed, n=args.n)
+    case = cases.pool512(seed=args.seed, n=args.n)
     prec = V.VFS_MIXED if args.precision == "mixed" else V.VFS_FP64
     stream = torch.cuda.current_stream()
 
@@ -341,12 +341,12 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
     ctx.close()
-    if not args.no_config3:
-        out["config3_fp64_vs_mixed"] = config3_leg(V)
-    if not args.no_config4:
-        out["config4_batched"] = config4_leg(V, check=not args.no_check)
-    if not args.no_config5:
-        out["config5_learned_vs_plain"] = config5_leg(V)
+    if not args.no_column128:
+        out["column128_fp64_vs_mixed"] = column128_leg(V)
+    if not args.no_batch64:
+        out["batch64_2d"] = batch64_leg(V, check=not args.no_check)
+    if not args.no_pool256:
+        out["pool256_learned_vs_plain"] = pool256_leg(V)
     print(json.dumps(out), flush=True)
 
 

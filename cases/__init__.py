@@ -15,13 +15,13 @@ Conventions (used by every consumer):
   * cell arrays (rho, mu): (nx, ny(, nz)).
 
 Workloads (one base seed each, recorded by the caller):
-  config1  2D 32^2 drop above a solid floor, FP64 reference case.
-  config2  2D 512^2 pool + 8 random circles + moving solid disc,
-           smooth log-uniform viscosity [1,1000] and density [0.5,2].
-  config3  3D 128^2 falling column with perturbed radius onto a floor.
-  config4  64 independent 2D problems, n in {64,96,...,512}, each shaped as
-           config1 with its own seed.
-  config5  3D 256^3 analogue of config2 (pool + 8 spheres + moving sphere).
+  drop32     2D 32^2 drop above a solid floor, FP64 reference case.
+  pool512    2D 512^2 pool + 8 random circles + moving solid disc,
+             smooth log-uniform viscosity [1,1000] and density [0.5,2].
+  column128  3D 128^3 falling column with perturbed radius onto a floor.
+  batch64    64 independent 2D problems, n in {64,96,...,512}, each shaped as
+             drop32 with its own seed.
+  pool256    3D 256^3 analogue of pool512 (pool + 8 spheres + moving sphere).
 """
 from __future__ import annotations
 
@@ -29,7 +29,7 @@ import numpy as np
 
 __all__ = [
     "node_coords", "face_coords", "cell_coords",
-    "config1", "config2", "config3", "config4", "config5", "make_config",
+    "drop32", "pool512", "column128", "batch64", "pool256",
     "drop2d", "pool2d", "pool3d", "column3d",
 ]
 
@@ -96,7 +96,7 @@ def _case(dim, n, h, origin, dt, phi_l, phi_s, rho, mu, u, u_bc, g, **meta):
 
 
 # --------------------------------------------------------------------------
-# 2D drop above a floor (config 1, and each member of config 4)
+# 2D drop above a floor (drop32, and each member of batch64)
 # --------------------------------------------------------------------------
 def drop2d(n, seed, dt=0.01, radius=0.35, centre=(0.5, 0.5), floor=0.1,
            sigma=0.1, rho=1.0, mu=1.0, g=(0.0, -1.0)):
@@ -112,14 +112,14 @@ def drop2d(n, seed, dt=0.01, radius=0.35, centre=(0.5, 0.5), floor=0.1,
                  name=f"drop2d_{n}", seed=seed)
 
 
-def config1(seed=1):
+def drop32(seed=1):
     c = drop2d(32, seed)
-    c.update(name="config1", tol=1e-10, precision="fp64")
+    c.update(name="drop32", tol=1e-10, precision="fp64")
     return c
 
 
 # --------------------------------------------------------------------------
-# 2D pool with random circles and a moving disc (config 2)
+# 2D pool with random circles and a moving disc (pool512)
 # --------------------------------------------------------------------------
 def pool2d(n, seed, dt=1e-3, n_circles=8, depth=0.3, g=(0.0, -1.0)):
     rng = np.random.default_rng(seed)
@@ -151,14 +151,14 @@ def pool2d(n, seed, dt=1e-3, n_circles=8, depth=0.3, g=(0.0, -1.0)):
                  name=f"pool2d_{n}", seed=seed, solid_velocity=tuple(V))
 
 
-def config2(seed=2, n=512):
+def pool512(seed=2, n=512):
     c = pool2d(n, seed)
-    c.update(name="config2", tol=1e-6, precision="mixed")
+    c.update(name="pool512", tol=1e-6, precision="mixed")
     return c
 
 
 # --------------------------------------------------------------------------
-# 3D falling column with a perturbed surface (config 3)
+# 3D falling column with a perturbed surface (column128)
 # --------------------------------------------------------------------------
 def column3d(n, seed, dt=1e-3, top=0.8, floor=0.1, radius=0.05, amp=0.01,
              mu=50.0, rho=1.0, speed=-0.5, g=(0.0, -9.8, 0.0)):
@@ -181,28 +181,28 @@ def column3d(n, seed, dt=1e-3, top=0.8, floor=0.1, radius=0.05, amp=0.01,
                  name=f"column3d_{n}", seed=seed)
 
 
-def config3(seed=3, n=128):
+def column128(seed=3, n=128):
     c = column3d(n, seed)
-    c.update(name="config3", tol=1e-6, precision="mixed")
+    c.update(name="column128", tol=1e-6, precision="mixed")
     return c
 
 
 # --------------------------------------------------------------------------
-# batched 2D (config 4)
+# batched 2D (batch64)
 # --------------------------------------------------------------------------
-def config4_sizes(seed=4, count=64):
+def batch64_sizes(seed=4, count=64):
     rng = np.random.default_rng(seed)
     return [int(v) for v in rng.choice(np.arange(64, 513, 32), size=count)]
 
 
-def config4(seed=4, count=64):
-    sizes = config4_sizes(seed, count)
+def batch64(seed=4, count=64):
+    sizes = batch64_sizes(seed, count)
     return [dict(drop2d(n, seed * 1000 + q), tol=1e-6, precision="mixed")
             for q, n in enumerate(sizes)]
 
 
 # --------------------------------------------------------------------------
-# 3D pool with random spheres and a moving sphere (config 5)
+# 3D pool with random spheres and a moving sphere (pool256)
 # --------------------------------------------------------------------------
 def pool3d(n, seed, dt=1e-3, n_spheres=8, depth=0.3, g=(0.0, -9.8, 0.0)):
     rng = np.random.default_rng(seed)
@@ -237,15 +237,10 @@ def pool3d(n, seed, dt=1e-3, n_spheres=8, depth=0.3, g=(0.0, -9.8, 0.0)):
                  name=f"pool3d_{n}", seed=seed, solid_velocity=tuple(V))
 
 
-def config5(seed=5, n=256):
+def pool256(seed=5, n=256):
     c = pool3d(n, seed)
-    c.update(name="config5", tol=1e-6, precision="mixed")
+    c.update(name="pool256", tol=1e-6, precision="mixed")
     return c
-
-
-def make_config(k, seed=None, **kw):
-    f = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[k]
-    return f(**kw) if seed is None else f(seed=seed, **kw)
 
 
 # --------------------------------------------------------------------------

@@ -3,7 +3,7 @@ infrastructure only; the product path never imports this module).
 
 The paper solves its SPD system with CG and an algebraic overlapping
 multiplicative Schwarz preconditioner (Section 8 end, Section 9).  The
-learned preconditioner is an addition of this build, not part of the paper;
+learned preconditioner is an addition to the method, not part of the paper;
 each piece below is written from its published definition:
 
 * U-Net style encoder/decoder (Ronneberger, Fischer and Brox 2015) on a

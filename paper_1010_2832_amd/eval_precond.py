@@ -45,7 +45,7 @@ def main(argv=None):
         net.vfs_unet_set_weights(np.load(a.weights, allow_pickle=False).astype(np.float32))
     for spec in a.cases:
         n, seed, cap = (int(q) for q in spec.split(":"))
-        c = cases.config5(n=n) if seed == 5 else cases.pool3d(n, seed=seed)
+        c = cases.pool256(n=n) if seed == 5 else cases.pool3d(n, seed=seed)
         ctx = V.context_from_case(c, precision=V.VFS_MIXED, tol=a.tol)
         if net is not None:
             ctx.vfs_set_preconditioner(net)

@@ -13,7 +13,7 @@ from oracle import system
 
 @pytest.mark.parametrize("make,lo,m", [
     (lambda: cases.pool3d(16, seed=3), (2, 3, 4), (11, 10, 11)),
-    (lambda: cases.config2(n=48), (9, 4, ), (26, 24)),
+    (lambda: cases.pool512(n=48), (9, 4, ), (26, 24)),
 ])
 def test_crop_interior_matches_full(make, lo, m):
     full = make()
@@ -41,7 +41,7 @@ def test_crop_interior_matches_full(make, lo, m):
 
 
 def test_crop_rejects_out_of_range():
-    c = cases.config1()
+    c = cases.drop32()
     with pytest.raises(ValueError):
         cases.crop(c, (30, 0), (8, 8))
     assert MARGIN >= 2

@@ -35,7 +35,7 @@ def _ragged_case(nx, ny, seed):
 
 
 CASES = {
-    "config1": lambda: cases.config1(),
+    "drop32": lambda: cases.drop32(),
     "ragged37x53": lambda: _ragged_case(37, 53, 1),
     "ragged130x67": lambda: _ragged_case(130, 67, 2),
     "E2_64": lambda: analytic.make_case("E2", 64),
@@ -103,7 +103,7 @@ def test_step_fp64_matches_oracle(name):
     assert system.true_relative_residual(asm, xg) <= 1e-10
 
 
-@pytest.mark.parametrize("name", ["config1", "ragged130x67", "E2_64"])
+@pytest.mark.parametrize("name", ["drop32", "ragged130x67", "E2_64"])
 def test_step_mixed_matches_oracle(name):
     _banner(f"step mixed {name}")
     case = CASES[name]()
@@ -119,11 +119,11 @@ def test_step_mixed_matches_oracle(name):
     assert st["n_tile_samples"] == expected_tile_samples(asm, (64, 12))
 
 
-def test_config2_full_size_mixed():
+def test_pool512_full_size_mixed():
     """512^2 pool with moving solid, variable mu and rho, mixed precision at
     the timing tolerance 1e-6, plus a tighter solve for the 1e-4 velocity bar."""
-    _banner("config2 512^2 mixed")
-    case = cases.config2()
+    _banner("pool512 512^2 mixed")
+    case = cases.pool512()
     asm, x, u = oracle(case)
     for tol, bar in ((1e-6, None), (1e-9, 1e-4)):
         ctx = gpu_run(case, precision=1, tol=tol)
@@ -143,7 +143,7 @@ def test_config2_full_size_mixed():
 
 def test_determinism_bitwise():
     _banner("determinism")
-    case = cases.config1()
+    case = cases.drop32()
     outs = []
     for _ in range(2):
         ctx = gpu_run(case, tol=1e-10)
@@ -156,7 +156,7 @@ def test_determinism_bitwise():
 def test_no_liquid_and_tiny_grids():
     _banner("degenerate cases")
     from paper_1010_2832_amd import vfstokes as V
-    c = cases.config1()
+    c = cases.drop32()
     c["phi_l"] = np.ones_like(c["phi_l"])        # all air
     ctx = gpu_run(c)
     st = ctx.vfs_get_stats()
@@ -175,7 +175,7 @@ def test_no_liquid_and_tiny_grids():
 def test_error_paths():
     _banner("error paths")
     from paper_1010_2832_amd import vfstokes as V
-    c = cases.config1()
+    c = cases.drop32()
     ctx = V.Context(2, c["n"], c["h"])
     bad = c["phi_l"].copy()
     bad[3, 4] = np.nan
@@ -204,7 +204,7 @@ def test_device_pointer_inputs_match_host_inputs():
     """Inputs passed as device tensors (already in HBM) give the same step."""
     import torch
     _banner("device pointers")
-    case = cases.config1()
+    case = cases.drop32()
     ctx = gpu_run(case, tol=1e-10)
     ref = flat_faces(system.Grid(case["n"], case["h"]), ctx.vfs_get_velocity())
     from paper_1010_2832_amd import vfstokes as V

@@ -125,15 +125,15 @@ def test_autotuner_picks_a_valid_configuration(tmp_path):
     b.close()
 
 
-def test_config4_full_size():
+def test_batch64_full_size():
     """64 problems with sizes drawn from {64, 96, ..., 512}^2, autotuned,
     mixed precision to 1e-6; oracle parity on the smallest, a middle and the
     largest problem; prints latency percentiles and aggregate DOF*iter/s."""
     from paper_1010_2832_amd import autotune
     from paper_1010_2832_amd import vfstokes as V
-    probs = cases.config4()
+    probs = cases.batch64()
     sizes = [c["n"][0] for c in probs]
-    _banner(f"config4: {len(probs)} problems, sizes {min(sizes)}..{max(sizes)}")
+    _banner(f"batch64: {len(probs)} problems, sizes {min(sizes)}..{max(sizes)}")
     b = V.batch_from_cases(probs, tol=1e-6)
     b.vfs_batch_step(probs[0]["dt"])
     res = autotune.tune(b, iterations=20, use_cache=False, cache_path=None)

@@ -49,16 +49,16 @@ def _sites_column(case):
     return [("column foot", (0.5, 0.1, 0.5)), ("column top", (0.5, 0.8, 0.5))]
 
 
-CONFIGS = {
-    "pool256": (lambda: cases.config5(), _sites_pool),
-    "column128": (lambda: cases.config3(), _sites_column),
+WORKLOADS = {
+    "pool256": (lambda: cases.pool256(), _sites_pool),
+    "column128": (lambda: cases.column128(), _sites_column),
 }
 
 
-@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("name", list(WORKLOADS))
 def test_fullsize_crops(name):
     from paper_1010_2832_amd import vfstokes as V
-    make, sites = CONFIGS[name]
+    make, sites = WORKLOADS[name]
     case = make()
     G = Grid(case["n"], case["h"], case.get("origin"))
     _banner(f"{name}: assemble {case['n']} on the GPU")
