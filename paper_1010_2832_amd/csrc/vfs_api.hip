@@ -521,7 +521,11 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         HIPCHK(hipStreamSynchronize(s));
         ctx->tiles.list = ctx->tile_list;
         ctx->tiles.count = *ctx->tile_count_host;
-        ctx->tiles.split = tile_split(ctx->tiles.count);
+        // main kernel of the solve: the fused FP32 iteration (mixed) or the
+        // pipelined FP64 direction + apply
+        const int cap = ctx->precision == VFS_MIXED ? fused3d_grid(1 << 30)
+                                                    : dir3d_grid(1 << 30, (int)sizeof(double));
+        ctx->tiles.split = tile_split(ctx->tiles.count, cap);
         ctx->stats.n_tile_samples = (int64_t)ctx->tiles.count * tile3d_anchors() * g.nsamp();
     }
     if (ctx->precision == VFS_MIXED) {

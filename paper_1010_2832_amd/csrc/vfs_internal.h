@@ -295,7 +295,7 @@ void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v
 // anchor positions of one tile of the 3D kernels and of the fused 2D kernel
 int tile3d_anchors();
 // plane split of a 3D tile list (Tiles::split)
-int tile_split(int count);
+int tile_split(int count, int capacity);
 int tile2d_anchors();
 // fused 2D CG over the compacted list of tiles holding an active sample
 void fused2d_tile_dims(const Geo& g, int& ntx, int& nty);
