@@ -954,6 +954,15 @@ int tile_split(int count, int capacity) {
     return split;
 }
 
+// The update is elementwise, with no halo and no plane-to-plane dependence:
+// a short tile list gives it one plane per work item (split KZ), as long as
+// that does not exceed the grid cap, whatever split the applies use.
+Tiles update3d_tiles(const Tiles& tl) {
+    Tiles tu = tl;
+    while (tu.split < KZ && (long long)tl.count * tu.split * 2 <= kMaxTileBlocks) tu.split *= 2;
+    return tu;
+}
+
 int apply3d_grid(int count, int word) { return resident_grid(count, word, false); }
 
 int dir3d_grid(int count, int word) { return resident_grid(count, word, true); }
@@ -1027,8 +1036,9 @@ template <typename T>
 void launch_update3d(const Geo& g, const Tiles& tl, T* x, const T* p, T* r, const T* q,
                      const T* dinv, T* z, const RedArgs& ra, hipStream_t s) {
     if (tl.count <= 0) return;
-    hipLaunchKernelGGL((k_update3d<T>), dim3(std::min(tl.items(), kMaxTileBlocks)), dim3(NT), 0, s, g,
-                       tl, x, p, r, q, dinv, z, ra);
+    const Tiles tu = update3d_tiles(tl);
+    hipLaunchKernelGGL((k_update3d<T>), dim3(std::min(tu.items(), kMaxTileBlocks)), dim3(NT), 0, s,
+                       g, tu, x, p, r, q, dinv, z, ra);
 }
 
 #define VFS_INST3(T)                                                                           \

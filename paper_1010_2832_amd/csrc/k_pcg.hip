@@ -395,7 +395,7 @@ int dir_apply_blocks(const Geo& g, const Tiles& tl, int word) {
 }
 
 int update_blocks(const Geo& g, const Tiles& tl) {
-    return g.dim == 2 ? vec_grid_blocks(g) : std::min(tl.items(), kMaxTileBlocks);
+    return g.dim == 2 ? vec_grid_blocks(g) : std::min(update3d_tiles(tl).items(), kMaxTileBlocks);
 }
 
 template <typename T>

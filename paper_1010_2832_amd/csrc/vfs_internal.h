@@ -296,6 +296,8 @@ void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v
 int tile3d_anchors();
 // plane split of a 3D tile list (Tiles::split)
 int tile_split(int count, int capacity);
+// the tile list as the 3D update kernel walks it (its own, finer split)
+Tiles update3d_tiles(const Tiles& tl);
 int tile2d_anchors();
 // fused 2D CG over the compacted list of tiles holding an active sample
 void fused2d_tile_dims(const Geo& g, int& ntx, int& nty);
