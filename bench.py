@@ -176,8 +176,9 @@ def batch64_leg(V, check=True):
 
 def pool256_leg(V, learned_cap=400):
     """Learned vs plain PCG on the 3D 256^3 configuration: Jacobi PCG in mixed
-    precision to 1e-6, then truncated flexible CG with the committed network
-    (capped at learned_cap iterations to bound the run) on the same step."""
+    precision to 1e-6, Jacobi PCG capped at learned_cap iterations, then
+    truncated flexible CG with the committed network (capped at learned_cap
+    iterations to bound the run) on the same step."""
     import numpy as np
     import cases
     case = cases.pool256()
@@ -194,6 +195,15 @@ def pool256_leg(V, learned_cap=400):
         "dof_iter_per_s": st["n_active"] * st["iterations"] / (st["t_solve_ms"] * 1e-3),
         "ms_per_iteration": st["t_solve_ms"] / max(1, st["iterations"]),
         "apply_avg_ms": st["t_apply_avg_ms"], "update_avg_ms": st["t_update_avg_ms"]}
+    # the same step, plain PCG capped at the learned solver's iteration count
+    ctx.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_MIXED, 1e-6, learned_cap)
+    ctx.vfs_set_velocity(case["u"])
+    ctx.vfs_set_profiling(True)
+    ctx.vfs_step(case["dt"], allow_unconverged=True)
+    sc = ctx.vfs_get_stats()
+    out["plain_jacobi_pcg_capped"] = {
+        "iteration_cap": learned_cap, "iterations": sc["iterations"], "solve_ms": sc["t_solve_ms"],
+        "rel_residual_fp64": sc["rel_residual"]}
     if os.path.exists(WEIGHTS):
         net = V.Unet()
         net.vfs_unet_set_weights(np.load(WEIGHTS, allow_pickle=False).astype(np.float32))
