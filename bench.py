@@ -95,7 +95,7 @@ def cpu_baseline(case, iters, seconds_cap=30.0):
             "assembly_s": t1 - t0}
 
 
-WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96.npy")
+WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96_long.npy")
 
 
 def column128_leg(V):
