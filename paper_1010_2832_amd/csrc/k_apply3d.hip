@@ -22,7 +22,7 @@
 namespace vfs {
 namespace {
 
-constexpr int TX = 64, TY = 4, KZ = 8, NT = 256;
+constexpr int TX = kTile3X, TY = kTile3Y, KZ = kTile3Z, NT = 256;
 constexpr int HX = TX + 2, HY = TY + 2;
 constexpr int FX = TX + 1, FY = TY + 1;
 

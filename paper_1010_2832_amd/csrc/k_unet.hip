@@ -809,7 +809,7 @@ __device__ __forceinline__ double safe_ratio(double num, double den) {
 // a1 from (r.D^-1 r, .) partials and (d.Ad) partials; r1 = r - a1 qd;
 // partials (r1.D^-1 r1, 0); coef[0] = a1.  Optionally also the FP64 pair
 // r64 -= a1 qd, e64 -= a1 d (training).
-__global__ __launch_bounds__(CT) void k_coarse_prep(long long n, const float* __restrict__ r,
+__global__ __launch_bounds__(CT) void k_coarse_prep(Geo g, Tiles tl, const float* __restrict__ r,
                                                     const float* __restrict__ qd,
                                                     const float* __restrict__ dinv,
                                                     const double* __restrict__ part_rdr, int nb_rdr,
@@ -826,8 +826,14 @@ __global__ __launch_bounds__(CT) void k_coarse_prep(long long n, const float* __
     const float a1 = (float)a1d;
     if (blockIdx.x == 0 && threadIdx.x == 0) coef[0] = a1d;
     double acc = 0.0;
-    for (long long t = blockIdx.x * (long long)CT + threadIdx.x; t < n;
-         t += (long long)gridDim.x * CT) {
+    // only the positions of the active tiles: elsewhere every input is zero
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long long rows = (long long)tl.count * g.nsamp() * kTile3Y * kTile3Z;
+    for (long long u = (long long)blockIdx.x * (CT / 64) + wv; u < rows;
+         u += (long long)gridDim.x * (CT / 64)) {
+        bool ok;
+        const long long t = tile_row_offset(g, tl, u, lane, g.nsamp(), ok);
+        if (!ok) continue;
         const float v = r[t] - a1 * qd[t];
         r1[t] = v;
         acc += (double)v * (double)dinv[t] * (double)v;
@@ -843,7 +849,7 @@ __global__ __launch_bounds__(CT) void k_coarse_prep(long long n, const float* __
 // w from (n.r1, ., .) and (n.An) partials; z = a1 d + w n; partials of
 // (z.r, then z.Q_i and r.D^-1 Q_i for the previous directions of truncated
 // flexible CG, zero past fh.mk); coef[1] = w.
-__global__ __launch_bounds__(CT) void k_coarse_finish(long long n, const float* __restrict__ d,
+__global__ __launch_bounds__(CT) void k_coarse_finish(Geo g, Tiles tl, const float* __restrict__ d,
                                                       const float* __restrict__ nv,
                                                       const float* __restrict__ r,
                                                       const float* __restrict__ dinv,
@@ -864,8 +870,14 @@ __global__ __launch_bounds__(CT) void k_coarse_finish(long long n, const float* 
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     const int mk = fh.mk;
-    for (long long t = blockIdx.x * (long long)CT + threadIdx.x; t < n;
-         t += (long long)gridDim.x * CT) {
+    // only the positions of the active tiles: elsewhere every input is zero
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long long rows = (long long)tl.count * g.nsamp() * kTile3Y * kTile3Z;
+    for (long long u = (long long)blockIdx.x * (CT / 64) + wv; u < rows;
+         u += (long long)gridDim.x * (CT / 64)) {
+        bool ok;
+        const long long t = tile_row_offset(g, tl, u, lane, g.nsamp(), ok);
+        if (!ok) continue;
         const float zi = a1 * d[t] + w * nv[t];
         z[t] = zi;
         const double ri = r[t], rd = ri * (double)dinv[t];
@@ -1073,22 +1085,20 @@ void launch_net_rdr(const Geo& g, const float* r, const float* dinv, double* par
 
 int coarse_blocks(const Geo& g) { return grid_for((long long)g.nsamp() * g.NP); }
 
-void launch_coarse_prep(const Geo& g, const float* r, const float* qd, const float* dinv,
-                        const double* part_rdr, int nb_rdr, const double* part_dq, int nb_dq,
-                        float* r1, double* part, double* coef, const float* d, double* r64,
-                        double* e64, const int* skip, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_prep, dim3(coarse_blocks(g)), dim3(CT), 0, s,
-                       (long long)g.nsamp() * g.NP, r, qd, dinv, part_rdr, nb_rdr, part_dq, nb_dq, r1,
-                       part, coef, d, r64, e64, skip);
+void launch_coarse_prep(const Geo& g, const Tiles& tl, const float* r, const float* qd,
+                        const float* dinv, const double* part_rdr, int nb_rdr,
+                        const double* part_dq, int nb_dq, float* r1, double* part, double* coef,
+                        const float* d, double* r64, double* e64, const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_prep, dim3(coarse_blocks(g)), dim3(CT), 0, s, g, tl, r, qd, dinv,
+                       part_rdr, nb_rdr, part_dq, nb_dq, r1, part, coef, d, r64, e64, skip);
 }
 
-void launch_coarse_finish(const Geo& g, const float* d, const float* nv, const float* r,
-                          const float* dinv, double* coef, const double* part_nr, int nb_nr,
-                          const double* part_nq, int nb_nq, const FcgHist& fh, float* z,
-                          double* part, const int* skip, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_finish, dim3(coarse_blocks(g)), dim3(CT), 0, s,
-                       (long long)g.nsamp() * g.NP, d, nv, r, dinv, coef, part_nr, nb_nr, part_nq,
-                       nb_nq, fh, z, part, skip);
+void launch_coarse_finish(const Geo& g, const Tiles& tl, const float* d, const float* nv,
+                          const float* r, const float* dinv, double* coef, const double* part_nr,
+                          int nb_nr, const double* part_nq, int nb_nq, const FcgHist& fh,
+                          float* z, double* part, const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_coarse_finish, dim3(coarse_blocks(g)), dim3(CT), 0, s, g, tl, d, nv, r,
+                       dinv, coef, part_nr, nb_nr, part_nq, nb_nq, fh, z, part, skip);
 }
 
 }  // namespace vfs

@@ -29,6 +29,8 @@ constexpr int kFront = 16;
 // 3D kernels run at most this many workgroups, each looping over tiles, so
 // that the partial sums a consumer must read stay few.
 constexpr int kMaxTileBlocks = 1536;
+// 3D tile: 64 x 4 anchors in x, y, marching 8 planes in z
+constexpr int kTile3X = 64, kTile3Y = 4, kTile3Z = 8;
 
 struct Geo {
     int dim;
@@ -127,6 +129,22 @@ struct Tiles {
     int split = 1;
     __host__ __device__ int items() const { return count * split; }
 };
+
+// Offset (slice s included) of lane `lane` in row u of the active 3D tiles:
+// row u is one 64-wide x run (fixed y, z and sample slice) of a tile, so an
+// elementwise kernel that gives each wave one row at a time touches only the
+// positions of active tiles.  ok is false past the grid's last anchor.
+__device__ __forceinline__ long long tile_row_offset(const Geo& g, const Tiles& tl, long long u,
+                                                     int lane, int ns, bool& ok) {
+    constexpr int R = kTile3Y * kTile3Z;
+    const int id = tl.list[u / (ns * R)];
+    const int rem = (int)(u % (ns * R));
+    const int s = rem / R, jj = (rem / kTile3Z) % kTile3Y, kk = rem % kTile3Z;
+    const int tx = id % tl.ntx, ty = (id / tl.ntx) % tl.nty, tz = id / (tl.ntx * tl.nty);
+    const int i = tx * kTile3X + lane, j = ty * kTile3Y + jj, k = tz * kTile3Z + kk;
+    ok = i <= g.nx && j <= g.ny && k <= g.nz;
+    return s * g.NP + (ok ? g.idx(i, j, k) : 0);
+}
 
 }  // namespace vfs
 

@@ -130,17 +130,18 @@ int net_rdr_blocks(const Geo& g);
 void launch_net_rdr(const Geo& g, const float* r, const float* dinv, double* part, hipStream_t s);
 void launch_f32_to_f64(const float* src, double* dst, long long n, hipStream_t s);
 
-// Two-level preconditioner step (see k_unet.hip).  Partial counts of both
-// kernels: coarse_blocks(g).
+// Two-level preconditioner step (see k_unet.hip), over the positions of the
+// active tiles tl (the other positions of every vector involved are zero).
+// Partial counts of both kernels: coarse_blocks(g).
 int coarse_blocks(const Geo& g);
-void launch_coarse_prep(const Geo& g, const float* r, const float* qd, const float* dinv,
-                        const double* part_rdr, int nb_rdr, const double* part_dq, int nb_dq,
-                        float* r1, double* part, double* coef, const float* d, double* r64,
-                        double* e64, const int* skip, hipStream_t s);
-void launch_coarse_finish(const Geo& g, const float* d, const float* nv, const float* r,
-                          const float* dinv, double* coef, const double* part_nr, int nb_nr,
-                          const double* part_nq, int nb_nq, const FcgHist& fh, float* z,
-                          double* part, const int* skip, hipStream_t s);
+void launch_coarse_prep(const Geo& g, const Tiles& tl, const float* r, const float* qd,
+                        const float* dinv, const double* part_rdr, int nb_rdr,
+                        const double* part_dq, int nb_dq, float* r1, double* part, double* coef,
+                        const float* d, double* r64, double* e64, const int* skip, hipStream_t s);
+void launch_coarse_finish(const Geo& g, const Tiles& tl, const float* d, const float* nv,
+                          const float* r, const float* dinv, double* coef, const double* part_nr,
+                          int nb_nr, const double* part_nq, int nb_nq, const FcgHist& fh,
+                          float* z, double* part, const int* skip, hipStream_t s);
 
 }  // namespace vfs
 

@@ -270,7 +270,7 @@ int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, co
     const RedArgs j1{ctx->sc, nullptr, 0, net_region(ctx, 0), 0, 0, nullptr, 0, skip};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, false, r, nullptr, dinv, nullptr, D, QD, a, c, K,
                         nullptr, j1, s);
-    launch_coarse_prep(g, r, QD, dinv, part_rdr, nb_rdr, net_region(ctx, 0), nbA, R1,
+    launch_coarse_prep(g, ctx->tiles, r, QD, dinv, part_rdr, nb_rdr, net_region(ctx, 0), nbA, R1,
                        net_region(ctx, 1), ctx->netcoef, nullptr, nullptr, nullptr, skip, s);
     // network on r1
     launch_net_scale(net_region(ctx, 1), coarse_blocks(g), ctx->sc, u->dscal, s);
@@ -282,7 +282,8 @@ int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, co
     const RedArgs j2{ctx->sc, nullptr, 0, net_region(ctx, 3), 0, 0, nullptr, 0, skip};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, true, nullptr, NV, dinv, nullptr, nullptr, QN, a,
                         c, K, nullptr, j2, s);
-    launch_coarse_finish(g, D, NV, r, dinv, ctx->netcoef, net_region(ctx, 2), net_unpack_blocks(g),
+    launch_coarse_finish(g, ctx->tiles, D, NV, r, dinv, ctx->netcoef, net_region(ctx, 2),
+                         net_unpack_blocks(g),
                          net_region(ctx, 3), nbA, fh, ctx->z32, net_region(ctx, 4), skip, s);
     if (hipGetLastError() != hipSuccess) return ufail(u, VFS_EHIP, "launch failed");
     return VFS_OK;
@@ -545,7 +546,8 @@ int vfs_unet_train_step(vfs_unet* u, vfs_ctx* ctx, const double* r, const double
     const RedArgs j1{ctx->sc, nullptr, 0, net_region(ctx, 0), 0, 0, nullptr, 0, nullptr};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, false, ctx->r32, nullptr, ctx->dinv32, nullptr, D,
                         QD, ctx->a32, ctx->c32, ctx->K32, nullptr, j1, s);
-    launch_coarse_prep(g, ctx->r32, QD, ctx->dinv32, u->dpart, net_rdr_blocks(g), net_region(ctx, 0),
+    launch_coarse_prep(g, ctx->tiles, ctx->r32, QD, ctx->dinv32, u->dpart, net_rdr_blocks(g),
+                       net_region(ctx, 0),
                        nbA, R1, net_region(ctx, 1), ctx->netcoef, D, ctx->r, ctx->z, nullptr, s);
     // network direction f of r1 and A f
     launch_net_scale(net_region(ctx, 1), coarse_blocks(g), ctx->sc, u->dscal, s);
