@@ -644,7 +644,11 @@ int grid_for(long long n) {
     return (int)std::max<long long>(1, std::min<long long>(kVecBlocks, (n + CT - 1) / CT));
 }
 
-__global__ __launch_bounds__(CT) void k_net_unpack(Geo g, Level L0, const float* __restrict__ y32,
+// Only the anchors of the active tiles are visited (one 64-wide row of anchors
+// per wave, all six sample sets of each anchor): every sample outside them has
+// D^-1 = 0, and z there keeps the zero the work space was cleared to.
+__global__ __launch_bounds__(CT) void k_net_unpack(Geo g, Tiles tl, Level L0,
+                                                   const float* __restrict__ y32,
                                                    const float* __restrict__ dinv,
                                                    const double* __restrict__ scale,
                                                    const float* __restrict__ r,
@@ -652,15 +656,21 @@ __global__ __launch_bounds__(CT) void k_net_unpack(Geo g, Level L0, const float*
                                                    float* __restrict__ z,
                                                    double* __restrict__ part, const int* skip) {
     if (skip && *skip) return;
-    const long long n = (long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     const double sd = *scale;
     const float inv = sd > 0.0 ? (float)(1.0 / sd) : 0.f;
     double zr = 0.0, zq = 0.0, rdq = 0.0;
-    for (long long e = blockIdx.x * (long long)CT + threadIdx.x; e < n;
-         e += (long long)gridDim.x * CT) {
-        const int i = (int)(e % (g.nx + 1)), j = (int)((e / (g.nx + 1)) % (g.ny + 1));
-        const int k = (int)(e / ((long long)(g.nx + 1) * (g.ny + 1)));
-        const long long o = g.idx(i, j, k);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long long rows = (long long)tl.count * kTile3Y * kTile3Z;
+    for (long long u = (long long)blockIdx.x * (CT / 64) + wv; u < rows;
+         u += (long long)gridDim.x * (CT / 64)) {
+        bool ok;
+        const long long o = tile_row_offset(g, tl, u, lane, 1, ok);
+        if (!ok) continue;
+        const int id = tl.list[u / (kTile3Y * kTile3Z)];
+        const int rem = (int)(u % (kTile3Y * kTile3Z));
+        const int i = (id % tl.ntx) * kTile3X + lane;
+        const int j = ((id / tl.ntx) % tl.nty) * kTile3Y + rem / kTile3Z;
+        const int k = (id / (tl.ntx * tl.nty)) * kTile3Z + rem % kTile3Z;
         const long long v = ((long long)k * L0.Y + j) * L0.X + i;
         const float4 ya = *reinterpret_cast<const float4*>(y32 + v * 8);
         const float4 yb = *reinterpret_cast<const float4*>(y32 + v * 8 + 4);
@@ -1037,11 +1047,11 @@ int net_unpack_blocks(const Geo& g) {
     return grid_for((long long)(g.nx + 1) * (g.ny + 1) * (g.nz + 1));
 }
 
-void launch_net_unpack(const Geo& g, const Level& L0, const float* y32, const float* dinv,
-                       const double* scale, const float* r, const float* q, float* z,
-                       double* part, const int* skip, hipStream_t s) {
-    hipLaunchKernelGGL(k_net_unpack, dim3(net_unpack_blocks(g)), dim3(CT), 0, s, g, L0, y32, dinv,
-                       scale, r, q, z, part, skip);
+void launch_net_unpack(const Geo& g, const Tiles& tl, const Level& L0, const float* y32,
+                       const float* dinv, const double* scale, const float* r, const float* q,
+                       float* z, double* part, const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL(k_net_unpack, dim3(net_unpack_blocks(g)), dim3(CT), 0, s, g, tl, L0, y32,
+                       dinv, scale, r, q, z, part, skip);
 }
 
 int train_dot_blocks(const Geo& g) { return grid_for((long long)g.nsamp() * g.NP); }

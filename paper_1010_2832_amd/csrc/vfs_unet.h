@@ -107,12 +107,13 @@ void launch_net_geometry(const Geo& g, const Level& L0, const double* WL, const 
 template <typename T>
 void launch_net_pack(const Geo& g, const Level& L0, const T* r, const T* dinv, const double* scale,
                      uint16_t* x, const int* skip, hipStream_t s);
-// z = sqrt(D^-1) y / s on samples (0 where D^-1 = 0 or s = 0); with
+// z = sqrt(D^-1) y / s on the samples of the active tiles (0 where D^-1 = 0 or
+// s = 0; z elsewhere is left as it is, zero in the cleared work space); with
 // partials: (z.r, z.q, r.D^-1 q) per workgroup -> part (nb = returned count)
 int net_unpack_blocks(const Geo& g);
-void launch_net_unpack(const Geo& g, const Level& L0, const float* y32, const float* dinv,
-                       const double* scale, const float* r, const float* q, float* z,
-                       double* part, const int* skip, hipStream_t s);
+void launch_net_unpack(const Geo& g, const Tiles& tl, const Level& L0, const float* y32,
+                       const float* dinv, const double* scale, const float* r, const float* q,
+                       float* z, double* part, const int* skip, hipStream_t s);
 // training: partials of (f.r, f.q, e.r) then the loss gradient pushed back to the
 // network output: gy = P^T sqrt(D^-1) dL/df / s (bf16, 16 channels)
 void launch_train_dots(const Geo& g, const float* f, const float* q, const double* r,

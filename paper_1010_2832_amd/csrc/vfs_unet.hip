@@ -277,7 +277,8 @@ int net_precond(vfs_unet* u, vfs_ctx* ctx, const float* r, const float* dinv, co
     launch_net_pack<float>(g, u->L[0], R1, dinv, u->dscal, u->x, skip, s);
     int rc = net_forward(u, s, skip);
     if (rc) return rc;
-    launch_net_unpack(g, u->L[0], u->y32, dinv, u->dscal, R1, R1, NV, net_region(ctx, 2), skip, s);
+    launch_net_unpack(g, ctx->tiles, u->L[0], u->y32, dinv, u->dscal, R1, R1, NV,
+                      net_region(ctx, 2), skip, s);
     // A n and the combination z = a1 d + w n
     const RedArgs j2{ctx->sc, nullptr, 0, net_region(ctx, 3), 0, 0, nullptr, 0, skip};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, true, nullptr, NV, dinv, nullptr, nullptr, QN, a,
@@ -554,8 +555,8 @@ int vfs_unet_train_step(vfs_unet* u, vfs_ctx* ctx, const double* r, const double
     launch_net_pack<float>(g, u->L[0], R1, ctx->dinv32, u->dscal, u->x, nullptr, s);
     rc = net_forward(u, s, nullptr);
     if (rc) return rc;
-    launch_net_unpack(g, u->L[0], u->y32, ctx->dinv32, u->dscal, nullptr, nullptr, NV, nullptr,
-                      nullptr, s);
+    launch_net_unpack(g, ctx->tiles, u->L[0], u->y32, ctx->dinv32, u->dscal, nullptr, nullptr,
+                      NV, nullptr, nullptr, s);
     const RedArgs j2{ctx->sc, nullptr, 0, net_region(ctx, 3), 0, 0, nullptr, 0, nullptr};
     launch_apply<float>(g, ctx->tiles, MODE_JDIR, true, nullptr, NV, ctx->dinv32, nullptr, nullptr,
                         QN, ctx->a32, ctx->c32, ctx->K32, nullptr, j2, s);
