@@ -16,6 +16,10 @@ time, in DOF*iter/s.  The roofline object reports the dominant kernel (in
 the 2D mixed inner solve the fused PCG iteration, one launch per iteration)
 against MI355X HBM peak, with its average launch duration measured live by
 HIP events on the context stream.
+
+After the GPU legs, one CPU leg times the oracle (cpu_baseline) and checks
+host copies of the GPU outputs against it (error_vs_fp64_oracle); nothing
+else in this script runs the oracle.
 """
 from __future__ import annotations
 
@@ -76,23 +80,105 @@ def measured_traffic():
     return float(t.group(1))
 
 
-def cpu_baseline(case, iters, seconds_cap=30.0):
-    """The oracle as it stands: assemble the explicit FP64 matrix and run a
-    fixed number of Jacobi-PCG iterations; DOF*iter/s on the host."""
-    import numpy as np  # noqa: F401
+def crop_errors(case, sites, got):
+    """A 3D result at full size against the oracle, which cannot assemble the
+    whole grid in the time of a bench run: it assembles sub-boxes of CROP^3
+    cells (cases.crop) at the given sites, and at every sample and face at
+    least MARGIN index steps inside one (where the oracle's values are the
+    full case's) measures the GPU's active set, the residual of the GPU
+    solution under the oracle's A and b (relative to the GPU's global |b|),
+    and the GPU velocity against the one the oracle recovers from the GPU
+    solution.  got: name -> host copies of solution and velocity (the first
+    also holding rhs and active)."""
+    import numpy as np
+    import cases
+    from cases.crop_maps import CROP, crop_lo, face_map, sample_map
+    from oracle import system
+    from oracle.grid import Grid
+    G = Grid(case["n"], case["h"], case.get("origin"))
+    first = next(iter(got.values()))
+    act = np.asarray(first["active"]).astype(bool)
+    nb = float(np.linalg.norm(first["rhs"][act]))
+    ufl = {k: np.concatenate([G.flat(q) for q in g["velocity"]]) for k, g in got.items()}
+    out = {"method": f"oracle on {CROP}^3 sub-boxes, samples at least 3 index steps inside",
+           "sub_boxes": [], "active_mask_identical": True}
+    worst = {k: [0.0, 0.0] for k in got}
+    for label, centre in sites(case):
+        lo = crop_lo(case, centre)
+        C = system.assemble(cases.crop(case, lo, (CROP,) * 3))
+        ci, fi = sample_map(G, C.grid, lo)
+        fci, ffi = face_map(G, C.grid, lo)
+        ca, fa = sample_map(G, C.grid, lo, 0)
+        out["sub_boxes"].append({"site": label, "lo": list(lo),
+                                 "active_compared": int(C.active[ci].sum())})
+        out["active_mask_identical"] &= bool(np.array_equal(act[fi], C.active[ci]))
+        live = C.K[fci] > 0
+        for k, g in got.items():
+            xc = np.zeros(C.grid.n_samples())
+            xc[ca] = g["solution"][fa]
+            r = (C.b_full - system.apply(C, xc))[ci][C.active[ci]]
+            uc = system.recover_velocity(C, xc * C.active)[fci][live]
+            du = np.abs(ufl[k][ffi][live] - uc).max() / max(np.abs(uc).max(), 1e-300)
+            worst[k][0] = max(worst[k][0], float(np.linalg.norm(r)) / nb)
+            worst[k][1] = max(worst[k][1], float(du))
+    for k, (rr, du) in worst.items():
+        out[k] = {"local_rel_residual_measured_by_oracle": rr,
+                  "velocity_rel_linf_vs_oracle_recovery": du}
+    return out
+
+
+def cpu_oracle_leg(case, iters, main_out, batch_out, baseline=True, check=True, extra3d=()):
+    """The CPU leg, and the only place this script runs the oracle.  It starts
+    after every GPU leg has finished and reads only host copies of their
+    outputs.
+
+    cpu_baseline: the oracle as it stands assembles the explicit FP64 matrix of
+    the bench workload and runs a fixed number of Jacobi-PCG iterations
+    (DOF*iter/s on the host).
+    error_vs_fp64_oracle: the GPU velocity, solution and active set of the
+    bench workload (main_out), and of the smallest batched problem
+    (batch_out), against the oracle's direct FP64 step; each 3D result in
+    extra3d ((key, case, sites, host copies)) on sub-boxes (crop_errors)."""
+    import numpy as np
     from oracle import cg, system
-    t0 = time.perf_counter()
-    asm = system.assemble(case)
-    A, b = asm.A.tocsr(), asm.b
-    t1 = time.perf_counter()
-    cg.fixed_iterations(A, b, iters)
-    t2 = time.perf_counter()
-    n_act = A.shape[0]
-    return {"value": n_act * iters / (t2 - t1), "unit": "DOF*iter/s", "cores": 1, "kind": "oracle",
+    res = {}
+
+    def compare(c, got):
+        asm, x, u = system.step(c)
+        ug = np.concatenate([asm.grid.flat(q) for q in got["velocity"]])
+        m = asm.K > 0
+        e = {"velocity_rel_linf": float(np.abs(ug[m] - u[m]).max() / np.abs(u[m]).max()),
+             "rel_residual_measured_by_oracle": float(
+                 system.true_relative_residual(asm, got["solution"]))}
+        if "active" in got:
+            e["active_mask_identical"] = bool(np.array_equal(got["active"], asm.active))
+        return e
+
+    if check and main_out is not None:
+        res["error_vs_fp64_oracle"] = compare(case, main_out)
+    if check and batch_out is not None:
+        e = compare(batch_out["case"], batch_out)
+        res["batch64_error_vs_fp64_oracle"] = {"problem": batch_out["problem"],
+                                               "n": batch_out["case"]["n"][0], **e}
+    for key, c3, sites, got in extra3d:
+        if check:
+            res[key] = crop_errors(c3, sites, got)
+    if baseline:
+        t0 = time.perf_counter()
+        asm = system.assemble(case)
+        A, b = asm.A.tocsr(), asm.b
+        t1 = time.perf_counter()
+        cg.fixed_iterations(A, b, iters)
+        t2 = time.perf_counter()
+        n_act = A.shape[0]
+        res["cpu_baseline"] = {
+            "value": n_act * iters / (t2 - t1), "unit": "DOF*iter/s", "cores": 1,
+            "kind": "oracle",
             "sample": f"{case['name']} {case['n'][0]}^{len(case['n'])}: oracle assembly "
                       f"({t1 - t0:.1f} s) then {iters} Jacobi-PCG iterations on the explicit "
                       f"scipy.sparse FP64 matrix ({t2 - t1:.1f} s, single-threaded SpMV)",
             "assembly_s": t1 - t0}
+    return res
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96_long.npy")
@@ -100,13 +186,15 @@ WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96_lon
 
 def column128_leg(V):
     """FP64 plain PCG against mixed PCG with iterative refinement on the 3D
-    128^3 column configuration, both to a 1e-6 FP64 relative residual."""
+    128^3 column configuration, both to a 1e-6 FP64 relative residual.
+    Returns with the figures host copies of both solutions and velocities
+    (and of the right-hand side and active set) for the CPU leg to check."""
     import numpy as np
     import cases
     case = cases.column128()
     out = {"workload": "3D 128^3 column (radius 0.05, top 0.8) on a solid floor, mu 50, rho 1, "
                        "u = (0,-0.5,0), g (0,-9.8,0), dt 1e-3, seed 3, both to 1e-6"}
-    vel = {}
+    vel, got = {}, {}
     for name, prec in (("fp64", V.VFS_FP64), ("mixed", V.VFS_MIXED)):
         ctx = V.context_from_case(case, precision=prec, tol=1e-6)
         ctx.vfs_set_profiling(True)
@@ -114,7 +202,10 @@ def column128_leg(V):
         ctx.vfs_set_velocity(case["u"])
         ctx.vfs_step(case["dt"])
         st = ctx.vfs_get_stats()
-        vel[name] = np.concatenate([np.ravel(q) for q in ctx.vfs_get_velocity()])
+        got[name] = {"velocity": ctx.vfs_get_velocity(), "solution": ctx.vfs_get_solution()}
+        if name == "fp64":
+            got[name].update(rhs=ctx.vfs_get_rhs(), active=ctx.vfs_get_active())
+        vel[name] = np.concatenate([np.ravel(q) for q in got[name]["velocity"]])
         out[name] = {"iterations": st["iterations"], "outer_iterations": st["outer_iterations"],
                      "solve_ms": st["t_solve_ms"], "step_ms": st["t_step_ms"],
                      "rel_residual_fp64": st["rel_residual"], "n_active": st["n_active"],
@@ -123,15 +214,16 @@ def column128_leg(V):
         ctx.close()
     scale = max(float(np.abs(vel["fp64"]).max()), 1e-300)
     out["velocity_rel_linf_mixed_vs_fp64"] = float(np.abs(vel["mixed"] - vel["fp64"]).max()) / scale
-    return out
+    return out, got
 
 
-def batch64_leg(V, check=True):
+def batch64_leg(V):
     """Many uneven 2D solves in one persistent, graph-captured launch: the 64
     problems of sizes {64, 96, ..., 512}^2, tile shape and workgroups per CU
     picked by the autotuner, mixed precision to 1e-6.  Reports the solve time,
-    aggregate DOF*iter/s, per-problem latency percentiles and, unless check is
-    off, the smallest problem's velocity against the FP64 oracle."""
+    aggregate DOF*iter/s and per-problem latency percentiles; returns with
+    them host copies of the smallest problem's velocity and solution for the
+    CPU leg to check."""
     import numpy as np
     import cases
     from paper_1010_2832_amd import autotune
@@ -159,26 +251,20 @@ def batch64_leg(V, check=True):
            "grid": st["grid"], "graph_used": bool(st["graph_used"]),
            "max_rel_residual_fp64": max(p["rel_residual"] for p in per),
            "max_iterations": st["max_iterations"]}
-    if check:
-        from oracle import system
-        i = int(np.argmin(sizes))
-        asm, x, u = system.step(probs[i])
-        ug = np.concatenate([asm.grid.flat(q) for q in b.vfs_batch_get_velocity(i)])
-        m = asm.K > 0
-        out["error_vs_fp64_oracle"] = {
-            "problem": i, "n": sizes[i],
-            "velocity_rel_linf": float(np.abs(ug[m] - u[m]).max() / np.abs(u[m]).max()),
-            "rel_residual_measured_by_oracle": float(
-                system.true_relative_residual(asm, b.vfs_batch_get_solution(i)))}
+    i = int(np.argmin(sizes))
+    got = {"problem": i, "case": probs[i], "velocity": b.vfs_batch_get_velocity(i),
+           "solution": b.vfs_batch_get_solution(i)}
     b.close()
-    return out
+    return out, got
 
 
 def pool256_leg(V, learned_cap=400):
     """Learned vs plain PCG on the 3D 256^3 configuration: Jacobi PCG in mixed
     precision to 1e-6, Jacobi PCG capped at learned_cap iterations, then
     truncated flexible CG with the committed network (capped at learned_cap
-    iterations to bound the run) on the same step."""
+    iterations to bound the run) on the same step.  Returns with the figures
+    host copies of the converged Jacobi-PCG solution, its velocity, the
+    right-hand side and the active set for the CPU leg to check."""
     import numpy as np
     import cases
     case = cases.pool256()
@@ -189,6 +275,8 @@ def pool256_leg(V, learned_cap=400):
     ctx.vfs_set_profiling(True)
     ctx.vfs_step(case["dt"])
     st = ctx.vfs_get_stats()
+    got = {"velocity": ctx.vfs_get_velocity(), "solution": ctx.vfs_get_solution(),
+           "rhs": ctx.vfs_get_rhs(), "active": ctx.vfs_get_active()}
     out["plain_jacobi_pcg"] = {
         "iterations": st["iterations"], "solve_ms": st["t_solve_ms"], "step_ms": st["t_step_ms"],
         "rel_residual_fp64": st["rel_residual"], "n_active": st["n_active"],
@@ -222,7 +310,7 @@ def pool256_leg(V, learned_cap=400):
         ctx.vfs_set_preconditioner(None)
         net.close()
     ctx.close()
-    return out
+    return out, got
 
 
 def main():
@@ -254,6 +342,7 @@ def main():
     import torch
 
     import cases
+    from cases import crop_maps
     from paper_1010_2832_amd import vfstokes as V
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -338,25 +427,31 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_,
                      "apply_avg_ms": ta, "update_avg_ms": tu},
     }
-    if not args.no_check:
-        from oracle import system
-        asm, x, u = system.step(case)
-        ug = np.concatenate([asm.grid.flat(q) for q in ctx.vfs_get_velocity()])
-        m = asm.K > 0
-        xg = ctx.vfs_get_solution()
-        out["error_vs_fp64_oracle"] = {
-            "velocity_rel_linf": float(np.abs(ug[m] - u[m]).max() / np.abs(u[m]).max()),
-            "rel_residual_measured_by_oracle": float(system.true_relative_residual(asm, xg)),
-            "active_mask_identical": bool(np.array_equal(ctx.vfs_get_active(), asm.active))}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
+    main_got = {"velocity": ctx.vfs_get_velocity(), "solution": ctx.vfs_get_solution(),
+                "active": ctx.vfs_get_active()}
     ctx.close()
+    batch_got, extra3d, got = None, [], None
     if not args.no_column128:
-        out["column128_fp64_vs_mixed"] = column128_leg(V)
+        out["column128_fp64_vs_mixed"], got = column128_leg(V)
+        extra3d.append(("column128_fp64_vs_mixed", cases.column128(), crop_maps.sites_column, got))
     if not args.no_batch64:
-        out["batch64_2d"] = batch64_leg(V, check=not args.no_check)
+        out["batch64_2d"], batch_got = batch64_leg(V)
     if not args.no_pool256:
-        out["pool256_learned_vs_plain"] = pool256_leg(V)
+        out["pool256_learned_vs_plain"], got = pool256_leg(V)
+        extra3d.append(("pool256_learned_vs_plain", cases.pool256(), crop_maps.sites_pool,
+                        {"plain_jacobi_pcg": got}))
+    del got
+    if not (args.no_check and args.no_cpu):
+        res = cpu_oracle_leg(case, args.cpu_iters, main_got, batch_got,
+                             baseline=not args.no_cpu, check=not args.no_check, extra3d=extra3d)
+        for key in ("error_vs_fp64_oracle", "cpu_baseline"):
+            if key in res:
+                out[key] = res[key]
+        if "batch64_error_vs_fp64_oracle" in res:
+            out["batch64_2d"]["error_vs_fp64_oracle"] = res["batch64_error_vs_fp64_oracle"]
+        for key, _, _, _ in extra3d:
+            if key in res:
+                out[key]["error_vs_fp64_oracle"] = res[key]
     print(json.dumps(out), flush=True)
 
 

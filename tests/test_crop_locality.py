@@ -1,13 +1,13 @@
 """The premise of the full-size GPU checks: the oracle's assembly of a
 sub-box (cases.crop) agrees exactly with its assembly of the whole case at
-every sample and face at least crop_util.MARGIN index steps inside the
+every sample and face at least cases.crop_maps.MARGIN index steps inside the
 sub-box (weights, coefficients, activity, right-hand side, rows of A, and the
 velocity recovered from a given solution)."""
 import numpy as np
 import pytest
 
 import cases
-from crop_util import MARGIN, face_map, sample_map
+from cases.crop_maps import MARGIN, face_map, sample_map
 from oracle import system
 
 

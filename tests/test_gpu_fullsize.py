@@ -1,7 +1,7 @@
 """Parity at full size: the 3D 256^3 pool configuration (mixed precision, as
 the benchmark runs it) and the 3D 128^3 column configuration, on the GPU in
 one piece, compared with the oracle on sub-boxes it can assemble
-(cases.crop).  At every sample and face at least crop_util.MARGIN index steps
+(cases.crop).  At every sample and face at least cases.crop_maps.MARGIN index steps
 inside a sub-box the oracle's values equal the full case's (pinned on the CPU
 by test_crop_locality), so there the GPU must give: bit-identical weights and
 active set, the right-hand side and A x to 1e-12, and, after the full-size
@@ -12,46 +12,21 @@ import numpy as np
 import pytest
 
 import cases
-from crop_util import face_map, sample_map
+from cases.crop_maps import CROP, crop_lo, face_map, sample_map, sites_column, sites_pool
 from gpu_util import flat_faces, gpu_run
 from oracle import system
 from oracle.grid import Grid
 
 pytestmark = pytest.mark.gpu
-CROP = 24
 
 
 def _banner(msg):
     print(f"[fullsize] {msg}", flush=True)
 
 
-def _lo(case, centre):
-    n, h = case["n"], case["h"]
-    return tuple(int(np.clip(round(centre[a] / h) - CROP // 2, 0, n[a] - CROP)) for a in range(3))
-
-
-def _sites_pool(case):
-    """Sub-boxes where the moving solid sphere meets the liquid (else a box
-    corner under the pool), on the pool surface and on a liquid sphere's
-    surface."""
-    h = case["h"]
-    ps = np.asarray(case["phi_s"])
-    pl = np.asarray(case["phi_l"])
-    contact = np.argwhere((np.abs(ps) < 2 * h) & (pl < 0))
-    solid = contact[len(contact) // 2] * h if len(contact) else np.array([0.05, 0.05, 0.05])
-    ny = pl.shape[1]
-    band = np.argwhere((np.abs(pl) < h) & (np.arange(ny)[None, :, None] * h > 0.45))
-    drop = band[len(band) // 2] * h
-    return [("solid sphere", solid), ("pool surface", (0.5, 0.3, 0.5)), ("liquid sphere", drop)]
-
-
-def _sites_column(case):
-    return [("column foot", (0.5, 0.1, 0.5)), ("column top", (0.5, 0.8, 0.5))]
-
-
 WORKLOADS = {
-    "pool256": (lambda: cases.pool256(), _sites_pool),
-    "column128": (lambda: cases.column128(), _sites_column),
+    "pool256": (lambda: cases.pool256(), sites_pool),
+    "column128": (lambda: cases.column128(), sites_column),
 }
 
 
@@ -76,7 +51,7 @@ def test_fullsize_crops(name):
     y = ctx.vfs_apply(x)
     crops = []
     for label, centre in sites(case):
-        lo = _lo(case, centre)
+        lo = crop_lo(case, centre)
         C = system.assemble(cases.crop(case, lo, (CROP,) * 3))
         ci, fi = sample_map(G, C.grid, lo)
         fci, ffi = face_map(G, C.grid, lo)
