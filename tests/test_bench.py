@@ -60,3 +60,45 @@ def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     # and so is a missing one
     monkeypatch.setattr(bench, "COUNTERS", str(tmp_path / "absent.md"))
     assert bench.measured_traffic() is None
+
+
+def test_cpu_oracle_leg_on_the_oracles_own_outputs():
+    """The CPU leg fed with the oracle's own step in place of GPU outputs
+    reports zero error everywhere (2D main line, a batched problem, a 3D
+    result on sub-boxes), and a planted velocity error shows up in the 3D
+    sub-box figure."""
+    import numpy as np
+
+    import cases
+    from cases import crop_maps
+    from oracle import system
+
+    c2 = cases.pool2d(48, 2)
+    c2.setdefault("name", "pool2d_48")
+    asm, x, u = system.step(c2)
+    main = {"velocity": system.split_faces(asm.grid, u), "solution": x,
+            "active": asm.active.astype(np.uint8)}
+    cb = cases.drop2d(40, 4)
+    ab, xb, ub = system.step(cb)
+    batch = {"problem": 0, "case": cb, "velocity": system.split_faces(ab.grid, ub), "solution": xb}
+    c3 = cases.column3d(36, 3)
+    a3, x3, u3 = system.step(c3)
+    v3 = system.split_faces(a3.grid, u3)
+    got3 = {"exact": {"velocity": v3, "solution": x3, "rhs": a3.b_full,
+                      "active": a3.active.astype(np.uint8)},
+            "planted": {"velocity": [q * (1.0 + 1e-5) for q in v3], "solution": x3}}
+    res = bench.cpu_oracle_leg(c2, 5, main, batch, baseline=True, check=True,
+                               extra3d=[("c3", c3, crop_maps.sites_column, got3)])
+    e = res["error_vs_fp64_oracle"]
+    assert e["velocity_rel_linf"] == 0.0 and e["active_mask_identical"]
+    assert e["rel_residual_measured_by_oracle"] < 1e-10
+    eb = res["batch64_error_vs_fp64_oracle"]
+    assert eb["velocity_rel_linf"] == 0.0 and eb["rel_residual_measured_by_oracle"] < 1e-10
+    e3 = res["c3"]
+    assert e3["active_mask_identical"] and len(e3["sub_boxes"]) == 2
+    assert all(b["active_compared"] > 0 for b in e3["sub_boxes"])
+    assert e3["exact"]["local_rel_residual_measured_by_oracle"] < 1e-10
+    assert e3["exact"]["velocity_rel_linf_vs_oracle_recovery"] < 1e-12
+    assert 5e-6 < e3["planted"]["velocity_rel_linf_vs_oracle_recovery"] < 2e-5
+    cb_ = res["cpu_baseline"]
+    assert cb_["kind"] == "oracle" and cb_["cores"] == 1 and cb_["value"] > 0
