@@ -550,7 +550,7 @@ __global__ void k_batch_reset_ctl(BatchCtl* ctl) {
 // phases, where the loop may end.  Problems therefore retire independently;
 // their completion time is the device wall clock at DONE.
 template <int BX, int BY>
-__global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
+__global__ __launch_bounds__(NT, 2) void k_batch_pcg(BatchArgs A) {
     extern __shared__ double lds_dyn[];
     float* lds32 = reinterpret_cast<float*>(lds_dyn);
     double* lds64 = lds_dyn;
@@ -729,7 +729,7 @@ __global__ __launch_bounds__(NT) void k_batch_pcg(BatchArgs A) {
 // ---------------------------------------------------------------------------
 // variants: (BX, BY) tile shapes
 // ---------------------------------------------------------------------------
-static const int kVar[kBatchVariants][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 2}};
+static const int kVar[kBatchVariants][2] = {{64, 4}, {64, 8}, {32, 8}, {128, 2}, {64, 12}, {64, 16}};
 
 void batch_tile_shape(int variant, int* bx, int* by) {
     *bx = kVar[variant][0];
@@ -756,7 +756,9 @@ void launch_batch_pcg(int variant, const BatchArgs& A, int grid, hipStream_t s) 
         case 0: launch_variant<64, 4>(0, A, grid, s); break;
         case 1: launch_variant<64, 8>(0, A, grid, s); break;
         case 2: launch_variant<32, 8>(0, A, grid, s); break;
-        default: launch_variant<128, 2>(0, A, grid, s); break;
+        case 3: launch_variant<128, 2>(0, A, grid, s); break;
+        case 4: launch_variant<64, 12>(0, A, grid, s); break;
+        default: launch_variant<64, 16>(0, A, grid, s); break;
     }
 }
 
@@ -765,7 +767,9 @@ void launch_batch_resid(int variant, const BatchArgs& A, int grid, hipStream_t s
         case 0: launch_variant<64, 4>(1, A, grid, s); break;
         case 1: launch_variant<64, 8>(1, A, grid, s); break;
         case 2: launch_variant<32, 8>(1, A, grid, s); break;
-        default: launch_variant<128, 2>(1, A, grid, s); break;
+        case 3: launch_variant<128, 2>(1, A, grid, s); break;
+        case 4: launch_variant<64, 12>(1, A, grid, s); break;
+        default: launch_variant<64, 16>(1, A, grid, s); break;
     }
 }
 
@@ -796,7 +800,9 @@ int batch_pcg_occupancy(int variant, int* blocks_per_cu) {
         case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<64, 4>, NT, l32); break;
         case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<64, 8>, NT, l32); break;
         case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<32, 8>, NT, l32); break;
-        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<128, 2>, NT, l32); break;
+        case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<128, 2>, NT, l32); break;
+        case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<64, 12>, NT, l32); break;
+        default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_pcg<64, 16>, NT, l32); break;
     }
     *blocks_per_cu = nb;
     return e == hipSuccess ? 0 : -1;

@@ -6,7 +6,7 @@
 
 namespace vfs {
 
-constexpr int kBatchVariants = 4;   // tile shapes (BX x BY): 64x4, 64x8, 32x8, 128x2
+constexpr int kBatchVariants = 6;   // tile shapes (BX x BY): 64x4, 64x8, 32x8, 128x2, 64x12, 64x16
 
 // One problem as seen by the batched kernels (pointers into its context).
 struct BProb {

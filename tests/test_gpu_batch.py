@@ -18,7 +18,7 @@ def _problems(sizes, seed=7):
     return [cases.drop2d(n, seed * 100 + q) for q, n in enumerate(sizes)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_batch_matches_oracle_every_tile_variant(variant):
     from paper_1010_2832_amd import vfstokes as V
     sizes = [24, 37, 64, 50, 33]
