@@ -427,6 +427,12 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_,
                      "apply_avg_ms": ta, "update_avg_ms": tu},
     }
+    out["paper_context"] = {
+        "timings": None,
+        "note": "the paper reports no wall-clock times, hardware or precision; its only solver "
+                "figures are PCG iteration counts with an overlapping multiplicative Schwarz "
+                "preconditioner (Table 1: 2D free-surface disk, 54 at 512^2 and 110 at 1024^2, "
+                "one step with dt = 1), against Jacobi PCG here"}
     main_got = {"velocity": ctx.vfs_get_velocity(), "solution": ctx.vfs_get_solution(),
                 "active": ctx.vfs_get_active()}
     ctx.close()
