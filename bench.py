@@ -57,6 +57,14 @@ def fused_bytes(precision, n_active):
     return 11.0 * word * n_active
 
 
+def fused3d_bytes(n_active):
+    """Bytes one fused 3D CG iteration (one launch of k_fused3d, FP32) must
+    move per active DOF: read r, q, p, D^-1, a, x, the sample coefficients c
+    (5 per 6 samples) and face K (3 per 6 samples), write r, x, p, q -> 34/3
+    values."""
+    return 34.0 / 3.0 * 4 * n_active
+
+
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused2d_pool512_mixed_counters.md")
 KERNEL_SOURCES = ("paper_1010_2832_amd/csrc/k_fused2d.hip", "paper_1010_2832_amd/csrc/vfs_reduce.h")
 
@@ -283,6 +291,12 @@ def pool256_leg(V, learned_cap=400):
         "dof_iter_per_s": st["n_active"] * st["iterations"] / (st["t_solve_ms"] * 1e-3),
         "ms_per_iteration": st["t_solve_ms"] / max(1, st["iterations"]),
         "apply_avg_ms": st["t_apply_avg_ms"], "update_avg_ms": st["t_update_avg_ms"]}
+    b3, t3 = fused3d_bytes(st["n_active"]), st["t_apply_avg_ms"]
+    a3 = b3 / (t3 * 1e-3) / 1e9 if t3 > 0 else 0.0
+    out["plain_jacobi_pcg"]["roofline"] = {
+        "bound": "hbm", "kernel": "k_fused3d (one launch per PCG iteration, FP32 vectors)",
+        "achieved": a3, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a3 / HBM_PEAK_GBS,
+        "traffic": None, "avg_launch_ms": t3, "algorithmic_bytes_per_launch": b3}
     # the same step, plain PCG capped at the learned solver's iteration count
     ctx.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_MIXED, 1e-6, learned_cap)
     ctx.vfs_set_velocity(case["u"])

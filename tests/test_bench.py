@@ -45,6 +45,9 @@ def test_algorithmic_bytes():
     assert bench.algorithmic_bytes(2, 1, n) == (7 * 4 * n, 7 * 4 * n)
     a3, u3 = bench.algorithmic_bytes(3, 2, n)
     assert a3 == pytest.approx((5 + 11 / 6) * 8 * n) and u3 == 7 * 8 * n
+    # fused 3D iteration: read r, q, p, D^-1, a, x, c (5/6), K (3/6), write r, x, p, q
+    assert bench.fused3d_bytes(38582254) == pytest.approx(1.749e9, rel=1e-3)
+    assert bench.fused3d_bytes(n) == pytest.approx((6 + 5 / 6 + 3 / 6 + 4) * 4 * n)
 
 
 def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
