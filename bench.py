@@ -67,25 +67,44 @@ def fused3d_bytes(n_active):
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_fused2d_pool512_mixed_counters.md")
 KERNEL_SOURCES = ("paper_1010_2832_amd/csrc/k_fused2d.hip", "paper_1010_2832_amd/csrc/vfs_reduce.h")
+COUNTERS_3D = os.path.join(ROOT, "profiles", "k_fused3d_pool256_mixed_counters.md")
+KERNEL_SOURCES_3D = ("paper_1010_2832_amd/csrc/k_apply3d.hip", "paper_1010_2832_amd/csrc/vfs_reduce.h",
+                     "paper_1010_2832_amd/csrc/vfs_internal.h")
+
+
+def _profiled_traffic(path, sources, label, row):
+    """The scaled HBM bytes per launch that a committed rocprofv3 counter
+    summary records in its table row `row`, or None if the summary is absent
+    or the kernel sources changed since the counters were taken (SHA-256 of
+    `sources` against the one recorded after `label`)."""
+    import hashlib
+    import re
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    m = re.search(r"sha256 \(" + re.escape(label) + r"\): ([0-9a-f]+)", text)
+    t = re.search(re.escape(row) + r" \| ([0-9.eE+-]+)", text)
+    if not m or not t or m.group(1) != h.hexdigest():
+        return None
+    return float(t.group(1))
 
 
 def measured_traffic():
     """HBM bytes per launch of the fused 2D CG kernel from the committed
     rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None if the kernel sources
     changed since the counters were taken (or the summary is absent)."""
-    import hashlib
-    import re
-    if not os.path.exists(COUNTERS):
-        return None
-    text = open(COUNTERS).read()
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    m = re.search(r"sha256 \(k_fused2d.hip \+ vfs_reduce.h\): ([0-9a-f]+)", text)
-    t = re.search(r"HBM traffic per launch \(bytes, scaled\) \| ([0-9.eE+-]+)", text)
-    if not m or not t or m.group(1) != h.hexdigest():
-        return None
-    return float(t.group(1))
+    return _profiled_traffic(COUNTERS, KERNEL_SOURCES, "k_fused2d.hip + vfs_reduce.h",
+                             "HBM traffic per launch (bytes, scaled)")
+
+
+def measured_traffic_3d():
+    """The same for the fused 3D CG kernel on the 256^3 pool."""
+    return _profiled_traffic(COUNTERS_3D, KERNEL_SOURCES_3D,
+                             "k_apply3d.hip + vfs_reduce.h + vfs_internal.h",
+                             "HBM traffic per launch (one PCG iteration)")
 
 
 def crop_errors(case, sites, got):
@@ -296,7 +315,7 @@ def pool256_leg(V, learned_cap=400):
     out["plain_jacobi_pcg"]["roofline"] = {
         "bound": "hbm", "kernel": "k_fused3d (one launch per PCG iteration, FP32 vectors)",
         "achieved": a3, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a3 / HBM_PEAK_GBS,
-        "traffic": None, "avg_launch_ms": t3, "algorithmic_bytes_per_launch": b3}
+        "traffic": measured_traffic_3d(), "avg_launch_ms": t3, "algorithmic_bytes_per_launch": b3}
     # the same step, plain PCG capped at the learned solver's iteration count
     ctx.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_MIXED, 1e-6, learned_cap)
     ctx.vfs_set_velocity(case["u"])

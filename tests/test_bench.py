@@ -65,6 +65,17 @@ def test_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     assert bench.measured_traffic() is None
 
 
+def test_3d_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+    text = open(bench.COUNTERS_3D).read()
+    recorded = float(re.search(r"HBM traffic per launch \(one PCG iteration\) \| ([0-9.eE+-]+)",
+                               text).group(1))
+    assert bench.measured_traffic_3d() == recorded
+    # an edit of any of the kernel's sources makes the figure stale
+    src = tmp_path / "k_apply3d.hip"
+    src.write_text(open(bench.os.path.join(bench.ROOT, bench.KERNEL_SOURCES_3D[0])).read() + "\n")
+    monkeypatch.setattr(bench, "KERNEL_SOURCES_3D", (str(src),) + bench.KERNEL_SOURCES_3D[1:])
+    assert bench.measured_traffic_3d() is None
+
 def test_cpu_oracle_leg_on_the_oracles_own_outputs():
     """The CPU leg fed with the oracle's own step in place of GPU outputs
     reports zero error everywhere (2D main line, a batched problem, a 3D
