@@ -45,3 +45,20 @@ def test_crop_rejects_out_of_range():
     with pytest.raises(ValueError):
         cases.crop(c, (30, 0), (8, 8))
     assert MARGIN >= 2
+
+
+def test_crop_boxes_stay_inside_the_grid():
+    """The sub-box corner of every site used by the full-size checks keeps a
+    CROP^3 box inside the grid, also for points at or beyond its faces."""
+    from cases.crop_maps import CROP, crop_lo, sites_column, sites_pool
+    case = cases.column3d(40, 3)
+    n = case["n"]
+    for centre in [(0.0, 0.0, 0.0), (1.0, 1.0, 1.0), (0.5, 0.5, 0.5), (-0.2, 1.3, 0.5)]:
+        lo = crop_lo(case, centre)
+        assert all(0 <= lo[a] <= n[a] - CROP for a in range(3)), (centre, lo)
+    mid = crop_lo(case, (0.5, 0.5, 0.5))
+    assert all(abs(mid[a] + CROP // 2 - n[a] // 2) <= 1 for a in range(3))
+    for label, centre in sites_column(case) + sites_pool(cases.pool3d(40, 5)):
+        assert len(centre) == 3, label
+        lo = crop_lo(case, centre)
+        assert all(0 <= lo[a] <= n[a] - CROP for a in range(3)), label
