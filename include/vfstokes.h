@@ -7,11 +7,11 @@
  * Coefficient Stokes Flow on Irregular Domains":
  *   u* = u^n + dt g                         (body force, Section 10)
  *   volume fractions W_L, W_F               (Section 5, Figs. 3-4)
- *   null-space elimination                  (Section 7)
+ *   null-space elimination                  (Section 8)
  *   SPD stress/pressure system A x = b      (eq. stokesmixedsystemspd,
- *                                            factored form of Section 8,
+ *                                            factored form of Section 7,
  *                                            moving-solid RHS of Section 6.2)
- *   preconditioned CG on A                  (Section 8 end, Section 9)
+ *   preconditioned CG on A                  (Section 7 end, Section 9)
  *   velocity recovery from the KKT velocity row (eq. stokesmixedsystem)
  *
  * Conventions for every entry point
@@ -271,7 +271,7 @@ int vfs_batch_get_stats(vfs_batch* b, vfs_batch_stats* out);
 
 /* ------------------------------------------------------------------------
  * Learned preconditioner (3D).  Not part of the paper, whose CG uses an
- * algebraic Schwarz preconditioner (Section 8 end, Section 9): a U-Net
+ * algebraic Schwarz preconditioner (Section 7 end, Section 9): a U-Net
  * style network (Ronneberger et al. 2015) maps a residual r to a correction
  * z inside flexible CG (Golub and Ye 1999, Notay 2000; Polak-Ribiere beta),
  * with the Jacobi direction D^-1 r whenever z is not a descent direction.

@@ -14,7 +14,7 @@ Time-Dependent, Variable Coefficient Stokes Flow on Irregular Domains"):
   fractions.py  volume fractions W_L, W_F of the sample control volumes
                 (Section 5, Figs. 3-4) by an exact simplex integrator
   operators.py  centred difference operators G and D (Section 5)
-  system.py     body force, coefficients, null-space elimination (Section 7
+  system.py     body force, coefficients, null-space elimination (Section 8
                 "Null Space Elimination"), the SPD (stress, pressure) system
                 and its right-hand side (eq. stokesmixedsystemspd and the
                 prescribed-velocity terms of Section 6), direct and CG

@@ -1,6 +1,6 @@
 """Plain Jacobi-preconditioned conjugate gradients on the explicit sparse A.
 
-The paper solves its SPD system with preconditioned CG (Section 8 end,
+The paper solves its SPD system with preconditioned CG (Section 7 end,
 Section 9 first paragraph); the preconditioner here is the diagonal of A,
 the simplest choice.  This is the CPU timing baseline and a second solver
 to cross-check the direct solve; it is written as the textbook algorithm

@@ -2,7 +2,7 @@
 infrastructure only; the product path never imports this module).
 
 The paper solves its SPD system with CG and an algebraic overlapping
-multiplicative Schwarz preconditioner (Section 8 end, Section 9).  The
+multiplicative Schwarz preconditioner (Section 7 end, Section 9).  The
 learned preconditioner is an addition to the method, not part of the paper;
 each piece below is written from its published definition:
 

@@ -5,10 +5,10 @@ Paper references (section / equation labels of the paper):
     eqs. stokesequations1-3, stokesfreesurface, stokessolidwall;
   * combined free-surface + solid KKT: eq. stokesmixedsystem;
   * Schur complement on the velocity block -> SPD system:
-    eq. stokesmixedsystemspd, in the factored form of Section 8
+    eq. stokesmixedsystemspd, in the factored form of Section 7
     ("Generalization and Further Factorization");
   * prescribed solid velocity right-hand side: Section 6.2;
-  * null-space elimination: Section 7;
+  * null-space elimination: Section 8;
   * body force: the fractional step of Section 10 (u* = u^n + dt g).
 
 With the trace-free reduced stresses (see operators.py) the discrete
@@ -219,7 +219,7 @@ def assemble(case, dt=None, w_min=1e-3):
 # ---------------------------------------------------------------------------
 def pressure_null_vector(asm):
     """Constant pressure on the active p samples (zero stress): the rank-1
-    null vector of enclosed domains (Section 7, last paragraph)."""
+    null vector of enclosed domains (Section 8, last paragraph)."""
     lo, hi = asm.grid.sample_offsets()["p"]
     c = np.zeros(asm.grid.n_samples())
     c[lo:hi] = 1.0

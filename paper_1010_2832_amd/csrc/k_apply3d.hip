@@ -2,7 +2,7 @@
 // active tiles (64 x 4 anchors in x,y times 8 planes in z).  Tiles without
 // any active sample hold zeros in every solver vector and are skipped.
 //
-// Apply (paper eq. stokesmixedsystemspd, factored form of Section 8):
+// Apply (paper eq. stokesmixedsystemspd, factored form of Section 7):
 // g = K (B x) on faces, y = B^T g + Dg x on samples.  A workgroup marches its
 // 8 z-planes keeping two planes of weighted samples (halo 1 in x,y) and two
 // planes of each face field in LDS, so every face value is formed once and

@@ -1,6 +1,6 @@
 // 3D assembly of the SPD stress/pressure system (paper eq.
-// stokesmixedsystemspd, factored form of Section 8), null-space elimination
-// (Section 7), moving-solid right-hand side (Section 6.2) and velocity
+// stokesmixedsystemspd, factored form of Section 7), null-space elimination
+// (Section 8), moving-solid right-hand side (Section 6.2) and velocity
 // recovery from the velocity row of eq. stokesmixedsystem.
 //
 // Samples (Section 5, Fig. 2): p, tau_xx, tau_yy at cells (tau_zz =

@@ -11,7 +11,7 @@
 // expansion error does not accumulate.  q = A p is always applied
 // explicitly (no recurrence for A p), so the iterates are those of plain PCG
 // up to the rounding of beta.  The matrix is the paper's
-// A = dt B^T K B + Dg (eq. stokesmixedsystemspd, factored form of Section 8),
+// A = dt B^T K B + Dg (eq. stokesmixedsystemspd, factored form of Section 7),
 // applied with the same LDS-tiled stencil as k_apply2d.
 //
 // Launch k >= 1, from the partials (r.z, p.q, q.D^-1 r, q.D^-1 q, r.r) of

@@ -1,5 +1,5 @@
 // Preconditioned conjugate gradients on A = dt B^T K B + Dg (paper eq.
-// stokesmixedsystemspd; the factored form of Section 8 is what makes the
+// stokesmixedsystemspd; the factored form of Section 7 is what makes the
 // matrix-free apply two sparse passes: faces g = K (B x), then samples
 // y = B^T g + Dg x).
 //

@@ -2,12 +2,12 @@
 
   * symmetry and positive definiteness by brute force on tiny random
     geometries (eq. stokesmixedsystemspd, null-space elimination of
-    Section 7);
+    Section 8);
   * agreement with a dense solve at 8x8;
   * equivalence of the Schur form with the full (u, tau, p) KKT system
     (eq. stokesmixedsystem; Section 6.2 right-hand side for moving solids);
   * minimum dissipation: the recovered velocity is the constrained
-    minimiser of the primal functional (Section 8);
+    minimiser of the primal functional (Section 7);
   * exact states claimed in Section 9: hydrostatic rest, rigid translation
     and rotation of a free-surface body, and co-motion with a moving solid;
   * first-order velocity convergence on the four closed-form 2D cases.
@@ -72,7 +72,7 @@ def test_spd_bruteforce(dim, n, seed):
 @pytest.mark.parametrize("seed", [0, 1])
 def test_spd_enclosed_has_exactly_the_pressure_constant(seed):
     """A liquid-filled box with an inner solid: pressure is defined up to a
-    constant (Section 7, last paragraph) and nothing else is singular."""
+    constant (Section 8, last paragraph) and nothing else is singular."""
     rng = np.random.default_rng(seed)
     n = 8
     X = cases.node_coords((n, n), 1.0 / n, (0.0, 0.0))
