@@ -58,6 +58,8 @@ extern "C" {
 /* preconditioners */
 #define VFS_PRECOND_NONE     0
 #define VFS_PRECOND_JACOBI   1   /* diagonal of A */
+#define VFS_PRECOND_IC       2   /* reserved for an incomplete-Cholesky factor: no such
+                                    factor is built, vfs_set_solver returns VFS_EINVAL */
 #define VFS_PRECOND_LEARNED  3   /* U-Net correction inside flexible CG (3D, VFS_MIXED;
                                     attach a network with vfs_set_preconditioner) */
 
@@ -66,7 +68,17 @@ extern "C" {
 #define VFS_MIXED  1   /* FP32 apply/vectors, FP64 reductions, FP64 residual
                           and iterative-refinement outer steps */
 
-/* sample sets for vfs_get_weights / vfs_get_active */
+/* sample types, in sample order (index of a block of a sample-order vector);
+ * the 3D-only types shift the 2D tau_xy to slot 3 */
+#define VFS_SAMPLE_P      0
+#define VFS_SAMPLE_TXX    1
+#define VFS_SAMPLE_TXY_2D 2
+#define VFS_SAMPLE_TYY    2   /* 3D */
+#define VFS_SAMPLE_TXY    3   /* 3D */
+#define VFS_SAMPLE_TXZ    4   /* 3D */
+#define VFS_SAMPLE_TYZ    5   /* 3D */
+
+/* sample sets for vfs_get_weights */
 #define VFS_SET_CELL    0   /* p, tau_xx, tau_yy */
 #define VFS_SET_FACE_X  1
 #define VFS_SET_FACE_Y  2
@@ -191,8 +203,16 @@ int vfs_get_solution(vfs_ctx* ctx, double* x);   /* sample order */
 int vfs_get_rhs(vfs_ctx* ctx, double* b);        /* sample order */
 /* W_L or W_F of a sample set (VFS_SET_*), native shape of that set. */
 int vfs_get_weights(vfs_ctx* ctx, int set, int which, double* out);
-/* 1 for active (not eliminated) samples, sample order. */
+/* 1 for active (not eliminated) samples, sample order.  A sample is active
+ * when its liquid weight is positive, no face of its stencil has positive
+ * fluid weight and zero liquid weight, and some face of its stencil carries
+ * K > 0 (the null-space elimination of Section 8); inactive samples hold
+ * their boundary value 0.  ESTATE before the first assembly. */
 int vfs_get_active(vfs_ctx* ctx, uint8_t* out);
+/* The same mask for one sample type (VFS_SAMPLE_*) in that type's native
+ * shape (cells for p, tau_xx, tau_yy; nodes or edges for the off-diagonal
+ * stresses).  EINVAL for a type the grid's dimension does not have. */
+int vfs_get_active_mask(vfs_ctx* ctx, int sample, uint8_t* out);
 int vfs_get_stats(vfs_ctx* ctx, vfs_stats* out);
 /* Turn live per-kernel timing on (1) or off (0); turning it on resets the
  * accumulated averages reported in vfs_stats.  Timing adds one event pair
@@ -332,6 +352,19 @@ int vfs_unet_train_step(vfs_unet* u, vfs_ctx* ctx, const double* r, const double
                         double* loss);
 /* Attach a network (not owned; NULL detaches) for VFS_PRECOND_LEARNED. */
 int vfs_set_preconditioner(vfs_ctx* ctx, vfs_unet* u);
+/* Load FP32 weights (the vfs_unet_set_weights layout, exactly
+ * vfs_unet_param_count() * 4 bytes; host or device memory, copied) into a
+ * network owned by the context (created on the first call, freed by
+ * vfs_destroy, run on the context's stream) and attach it as by
+ * vfs_set_preconditioner.  EINVAL for a 2D context, a size mismatch or
+ * NaN/Inf weights. */
+int vfs_load_preconditioner(vfs_ctx* ctx, const void* weights, size_t bytes);
+/* One training pair from two iterates of a solve on the assembled context
+ * (sample order, FP64): r = b - A x_k and e = x_star - x_k on the active
+ * samples (0 on the others).  With x_star the solution of A x = b, A e = r:
+ * e is the exact correction of the residual r. */
+int vfs_training_pair(vfs_ctx* ctx, const double* x_star, const double* x_k, double* r,
+                      double* e);
 /* z = network correction of r on the assembled context (sample order). */
 int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z);
 

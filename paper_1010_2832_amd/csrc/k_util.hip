@@ -73,6 +73,14 @@ __global__ void k_mask(double* __restrict__ d, const double* __restrict__ s,
     if (t < n) d[t] = a[t] != 0.0 ? s[t] : 0.0;
 }
 
+// d = (x - y) on the samples with a != 0, 0 elsewhere
+__global__ void k_sub_mask(double* __restrict__ d, const double* __restrict__ x,
+                           const double* __restrict__ y, const double* __restrict__ a,
+                           long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) d[t] = a[t] != 0.0 ? x[t] - y[t] : 0.0;
+}
+
 inline unsigned nblk(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -118,6 +126,12 @@ void launch_to_f32(const double* src, float* dst, long long n, hipStream_t s) {
 void launch_mask(double* dst, const double* src, const double* a, long long n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_mask, dim3(nblk(n, 256)), dim3(256), 0, s, dst, src, a, n);
+}
+
+void launch_sub_mask(double* dst, const double* x, const double* y, const double* a, long long n,
+                     hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sub_mask, dim3(nblk(n, 256)), dim3(256), 0, s, dst, x, y, a, n);
 }
 
 }  // namespace vfs

@@ -660,6 +660,7 @@ int vfs_destroy(vfs_ctx* ctx) {
                     ctx->f32b,  ctx->fpart};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    if (ctx->net_owned) (void)vfs_unet_destroy(ctx->net_owned);
     if (ctx->tile_flags) (void)hipFree(ctx->tile_flags);
     if (ctx->tile_list) (void)hipFree(ctx->tile_list);
     if (ctx->tile_count) (void)hipFree(ctx->tile_count);
@@ -788,6 +789,7 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
 int vfs_set_stream(vfs_ctx* ctx, void* hip_stream) {
     if (!ctx) return VFS_EINVAL;
     ctx->stream = (hipStream_t)hip_stream;
+    if (ctx->net_owned) (void)vfs_unet_set_stream(ctx->net_owned, hip_stream);
     return VFS_OK;
 }
 
@@ -876,6 +878,9 @@ int vfs_set_gravity(vfs_ctx* ctx, const double* g) {
 int vfs_set_solver(vfs_ctx* ctx, int precond, int precision, double rel_tol, int max_iter,
                    double w_min) {
     if (!ctx) return VFS_EINVAL;
+    if (precond == VFS_PRECOND_IC)
+        return fail(ctx, VFS_EINVAL, "VFS_PRECOND_IC is reserved: no incomplete-Cholesky "
+                                     "preconditioner is built in this library");
     if (precond != VFS_PRECOND_JACOBI && precond != VFS_PRECOND_LEARNED)
         return fail(ctx, VFS_EINVAL, "unsupported preconditioner");
     if (precision != VFS_FP64 && precision != VFS_MIXED)
@@ -1016,6 +1021,43 @@ int vfs_get_weights(vfs_ctx* ctx, int set, int which, double* out) {
         return fail(ctx, VFS_EINVAL, "bad weight kind");
     const double* src = (which == VFS_WEIGHT_LIQUID ? ctx->WL : ctx->WF) + internal * ctx->g.NP;
     return get_set(ctx, internal, src, out);
+}
+
+int vfs_get_active_mask(vfs_ctx* ctx, int sample, uint8_t* out) {
+    if (!ctx || !out) return ctx ? fail(ctx, VFS_EINVAL, "NULL output") : VFS_EINVAL;
+    if (!ctx->assembled) return fail(ctx, VFS_ESTATE, "nothing assembled");
+    const Geo& g = ctx->g;
+    if (sample < 0 || sample >= g.nsamp()) return fail(ctx, VFS_EINVAL, "bad sample type");
+    int shp[3];
+    set_shape(g, sample_set(g.dim, sample), shp);
+    const long long n = (long long)shp[0] * shp[1] * shp[2];
+    uint8_t* stage8 = (uint8_t*)ctx->stage;
+    launch_unpack_active(g, shp, ctx->a + sample * g.NP, stage8, ctx->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, stage8, (size_t)n, hipMemcpyDefault, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return VFS_OK;
+}
+
+int vfs_training_pair(vfs_ctx* ctx, const double* x_star, const double* x_k, double* r,
+                      double* e) {
+    if (!ctx || !x_star || !x_k || !r || !e)
+        return ctx ? fail(ctx, VFS_EINVAL, "NULL vector") : VFS_EINVAL;
+    if (!ctx->assembled) return fail(ctx, VFS_ESTATE, "call vfs_assemble first");
+    const Geo& g = ctx->g;
+    // solver work vectors serve as staging: every solve re-initialises them
+    int rc = pack_samples(ctx, x_k, ctx->z);
+    if (rc) return rc;
+    rc = pack_samples(ctx, x_star, ctx->p0);
+    if (rc) return rc;
+    Scalars so{};
+    rc = true_residual(ctx, ctx->b, ctx->z, &so);   // ctx->r = b - A x_k
+    if (rc) return rc;
+    launch_sub_mask(ctx->q, ctx->p0, ctx->z, ctx->a, (long long)g.nsamp() * g.NP, ctx->stream);
+    HIPCHK(hipGetLastError());
+    rc = unpack_samples(ctx, ctx->r, r);
+    if (rc) return rc;
+    return unpack_samples(ctx, ctx->q, e);
 }
 
 int vfs_get_active(vfs_ctx* ctx, uint8_t* out) {

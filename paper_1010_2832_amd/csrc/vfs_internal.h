@@ -233,6 +233,7 @@ struct vfs_ctx {
     // learned preconditioner (not owned) and its work space: 5 FP32 sample
     // vectors (d, A d, r1, n, A n), partial regions, line-search coefficients
     struct vfs_unet* net = nullptr;
+    struct vfs_unet* net_owned = nullptr;  // created by vfs_load_preconditioner
     float* netvec = nullptr;
     double* netpart = nullptr;
     double* netcoef = nullptr;
@@ -288,6 +289,8 @@ void launch_check(const double* v, long long n, int positive, int* flag, hipStre
 void launch_zero_box_faces(const Geo& g, double* faces, hipStream_t s);
 void launch_to_f32(const double* src, float* dst, long long n, hipStream_t s);
 void launch_mask(double* dst, const double* src, const double* a, long long n, hipStream_t s);
+void launch_sub_mask(double* dst, const double* x, const double* y, const double* a, long long n,
+                     hipStream_t s);
 
 // CG building blocks (k_pcg.hip); T = double or float
 // MODE_FDIR: flexible-CG direction from a given z (or the Jacobi z when the

@@ -585,6 +585,25 @@ int vfs_set_preconditioner(vfs_ctx* ctx, vfs_unet* u) {
     return VFS_OK;
 }
 
+int vfs_load_preconditioner(vfs_ctx* ctx, const void* weights, size_t bytes) {
+    if (!ctx) return VFS_EINVAL;
+    if (!weights) return ctx_fail(ctx, VFS_EINVAL, "weights pointer is NULL");
+    if (ctx->g.dim != 3) return ctx_fail(ctx, VFS_EINVAL, "the learned preconditioner is 3D only");
+    if (bytes != (size_t)vfs_unet_param_count() * sizeof(float))
+        return ctx_fail(ctx, VFS_EINVAL, "weight bytes do not match the network's FP32 weights");
+    if (!ctx->net_owned) {
+        vfs_unet* u = nullptr;
+        int rc = vfs_unet_create(&u);
+        if (rc) return ctx_fail(ctx, rc, std::string("network: ") + vfs_unet_last_error(nullptr));
+        ctx->net_owned = u;
+    }
+    vfs_unet* u = ctx->net_owned;
+    u->stream = ctx->stream;
+    int rc = vfs_unet_set_weights(u, (const float*)weights, vfs_unet_param_count());
+    if (rc) return ctx_fail(ctx, rc, std::string("network: ") + u->err);
+    return vfs_set_preconditioner(ctx, u);
+}
+
 int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z) {
     if (!ctx) return VFS_EINVAL;
     if (!r || !z) return ctx_fail(ctx, VFS_EINVAL, "NULL vector");

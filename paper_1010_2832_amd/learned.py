@@ -57,9 +57,7 @@ def make_pairs(ctx, dt, ks, tol=1e-10, max_iter=200000, device=None):
         else:
             ctx.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_FP64, 1e-14, int(k), w_min)
             xk = ctx.vfs_solve(b, allow_unconverged=True)
-        r = b - ctx.vfs_apply(xk)
-        e = xs - xk
-        pairs.append((r, e))
+        pairs.append(ctx.vfs_training_pair(xs, xk))
     if saved is not None:
         ctx.vfs_set_solver(*saved)
     if device is not None:

@@ -17,7 +17,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvfstokes.so")
 
 VFS_OK, VFS_EINVAL, VFS_ENOMEM, VFS_EHIP, VFS_ENOTCONV, VFS_EBREAKDOWN, VFS_ESTATE = 0, -1, -2, -3, -4, -5, -6
-VFS_PRECOND_NONE, VFS_PRECOND_JACOBI, VFS_PRECOND_LEARNED = 0, 1, 3
+VFS_PRECOND_NONE, VFS_PRECOND_JACOBI, VFS_PRECOND_IC, VFS_PRECOND_LEARNED = 0, 1, 2, 3
+VFS_SAMPLE_P, VFS_SAMPLE_TXX = 0, 1
+VFS_SAMPLE_TXY_2D = 2
+VFS_SAMPLE_TYY, VFS_SAMPLE_TXY, VFS_SAMPLE_TXZ, VFS_SAMPLE_TYZ = 2, 3, 4, 5
 VFS_FP64, VFS_MIXED = 0, 1
 VFS_SET_CELL, VFS_SET_FACE_X, VFS_SET_FACE_Y, VFS_SET_FACE_Z = 0, 1, 2, 3
 VFS_SET_NODE = VFS_SET_EDGE_Z = 4
@@ -104,6 +107,8 @@ _SIGS = {
     "vfs_get_rhs": ([_P, _P], _I),
     "vfs_get_weights": ([_P, _I, _I, _P], _I),
     "vfs_get_active": ([_P, _P], _I),
+    "vfs_get_active_mask": ([_P, _I, _P], _I),
+    "vfs_training_pair": ([_P, _P, _P, _P, _P], _I),
     "vfs_get_stats": ([_P, ctypes.POINTER(vfs_stats)], _I),
     "vfs_get_sizes": ([_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)], _I),
     "vfs_set_profiling": ([_P, _I], _I),
@@ -138,6 +143,7 @@ _SIGS = {
     "vfs_unet_adam": ([_P, _D, _D, _D, _D, _D], _I),
     "vfs_unet_train_step": ([_P, _P, _P, _P, ctypes.POINTER(_D)], _I),
     "vfs_set_preconditioner": ([_P, _P], _I),
+    "vfs_load_preconditioner": ([_P, _P, ctypes.c_size_t], _I),
     "vfs_precond_apply": ([_P, _P, _P], _I),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -389,6 +395,21 @@ class Context:
         _check(self.handle, _lib.vfs_get_active(self.handle, out.ctypes.data))
         return out.astype(bool)
 
+    def vfs_get_active_mask(self, sample):
+        shp = self.sample_shapes()[sample] if 0 <= sample < len(self.sample_shapes()) else (0,)
+        out = np.zeros(int(np.prod(shp)), dtype=np.uint8)
+        _check(self.handle, _lib.vfs_get_active_mask(self.handle, sample, out.ctypes.data))
+        return out.reshape(shp, order="F").astype(bool)
+
+    def vfs_training_pair(self, x_star, x_k):
+        k = _Keep()
+        n = self.n_samples()
+        r = np.zeros(n)
+        e = np.zeros(n)
+        _check(self.handle, _lib.vfs_training_pair(self.handle, k.ptr(x_star, n), k.ptr(x_k, n),
+                                                   r.ctypes.data, e.ctypes.data))
+        return r, e
+
     def vfs_get_stats(self):
         st = vfs_stats()
         _check(self.handle, _lib.vfs_get_stats(self.handle, ctypes.byref(st)))
@@ -407,6 +428,12 @@ class Context:
         self._net = net   # the context does not own the network; keep it alive
         return _check(self.handle, _lib.vfs_set_preconditioner(self.handle,
                                                                net.handle if net else None))
+
+    def vfs_load_preconditioner(self, weights):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).ravel())
+        self._net = None   # the context owns the network it loads
+        return _check(self.handle, _lib.vfs_load_preconditioner(self.handle, w.ctypes.data,
+                                                                w.nbytes))
 
     def vfs_precond_apply(self, r):
         k = _Keep()

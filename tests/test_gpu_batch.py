@@ -150,8 +150,9 @@ def test_batch64_full_size():
         assert pr["rel_residual"] <= 1e-6
         _banner(f"  problem {i} n={sizes[i]} {pr}")
     b.close()
-    # parity: a fresh batch, one step, against the oracle on three problems
-    b = V.batch_from_cases(probs, tol=1e-9)
+    # parity at the tolerance the benchmark reports (bench.BATCH_TOL): a fresh
+    # batch, one step, against the oracle on three problems
+    b = V.batch_from_cases(probs, tol=1e-7)
     b.vfs_batch_step(probs[0]["dt"])
     for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
         asm, x, u = system.step(probs[i])

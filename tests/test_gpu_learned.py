@@ -8,9 +8,13 @@ Tolerances: both sides round to bfloat16 at the same points (inputs,
 weights, every stored activation and activation gradient); they differ in
 accumulation (FP32 on the GPU, FP64 in the oracle) and hence occasionally in
 the rounding of one stored value by one bfloat16 unit (2^-8 relative), which
-propagates.  The bars are relative 2-norm errors of 2e-2 for outputs and
-5e-2 for weight gradients (several stored-value flips per layer through
-eight layers), and 1e-6 relative for Adam (FP32 arithmetic)."""
+propagates.  Outputs and gradients are compared element by element: every
+entry must lie within FLIP_WORST of the tensor's largest magnitude (per
+layer for weight gradients, per output channel for the network output), and
+at most a fraction FLIP_FRAC of the entries (and never more than a handful
+in a small tensor) may differ by more than FLIP_FAR, four bfloat16 units at
+that magnitude; the rest agree to FP32 accumulation order.  Adam is held to
+1e-6 relative (FP32 arithmetic)."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -39,6 +43,33 @@ def L():
     return learned
 
 
+FLIP_FAR = 2.0 ** -6      # four bfloat16 units at the tensor's largest magnitude
+FLIP_FRAC = 2e-3          # share of entries allowed beyond FLIP_FAR (rounding flips)
+FLIP_WORST = 2.0 ** -3    # no entry may be further off than this
+
+
+def _flip_check(tag, got, ref, groups=None):
+    """Element-wise comparison with an allowance for bfloat16 rounding flips.
+    groups: optional integer label per entry (output channel, layer); each
+    group is judged against its own largest magnitude."""
+    got = np.asarray(got, np.float64).ravel()
+    ref = np.asarray(ref, np.float64).ravel()
+    assert got.shape == ref.shape, tag
+    labels = np.zeros(ref.size, np.int64) if groups is None else np.asarray(groups).ravel()
+    worst, far = 0.0, 0
+    for gid in np.unique(labels):
+        m = labels == gid
+        scale = max(np.abs(ref[m]).max(), 1e-30)
+        d = np.abs(got[m] - ref[m]) / scale
+        worst = max(worst, float(d.max()))
+        far += int((d > FLIP_FAR).sum())
+    allowed = max(4, int(FLIP_FRAC * ref.size))
+    _banner(f"  {tag}: {ref.size} entries, {far} beyond {FLIP_FAR:.3g} of scale "
+            f"(allowed {allowed}), worst {worst:.2e}, 2-norm rel {_rel(got, ref):.2e}")
+    assert far <= allowed, (tag, far, allowed)
+    assert worst <= FLIP_WORST, (tag, worst)
+
+
 def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
 
@@ -54,18 +85,18 @@ def test_network_forward_and_gradient_match_oracle(V, L, dims):
     net.vfs_unet_set_weights(w)
     y = net.vfs_unet_forward(x)
     y_o, cache = OL.forward(w.astype(np.float64), x.astype(np.float64), bf16_mode=True)
-    err = _rel(y, y_o)
-    _banner(f"  forward rel err {err:.2e}")
-    assert err <= 2e-2
+    assert y.shape == y_o.shape
+    _flip_check("forward output", y, y_o, groups=np.broadcast_to(np.arange(6), y_o.shape))
     gy = rng.normal(size=(Z, Y, X, 6)).astype(np.float32)
     net.vfs_unet_backward(gy)
     g = net.vfs_unet_get_grad()
     g_o = OL.backward(cache, gy.astype(np.float64), bf16_mode=True)
     offs = np.cumsum([0] + OL.layer_sizes())
     for layer in range(8):
-        e = _rel(g[offs[layer]:offs[layer + 1]], g_o[offs[layer]:offs[layer + 1]])
-        _banner(f"  layer {layer} weight-gradient rel err {e:.2e}")
-        assert e <= 5e-2, (layer, e)
+        sl = slice(offs[layer], offs[layer + 1])
+        cin, cout = L.LAYERS[layer]
+        _flip_check(f"layer {layer} weight gradient", g[sl], g_o[sl],
+                    groups=np.repeat(np.arange(cout), cin * 27))
     # a second backward accumulates
     net.vfs_unet_backward(gy)
     assert np.allclose(net.vfs_unet_get_grad(), 2 * g, rtol=1e-5, atol=1e-6 * np.abs(g).max())
@@ -154,9 +185,7 @@ def test_precond_apply_matches_oracle(V, L, small):
         y, _ = OL.forward(w.astype(np.float64), x, bf16_mode=True)
         return OL.unpack_output(asm, y, dinv, s)
     z_o = OL.two_level(apply_full, dinv, r, network)
-    err = _rel(z, z_o)
-    _banner(f"precond apply rel err {err:.2e}")
-    assert err <= 2e-2
+    _flip_check("precond apply", z[asm.active], z_o[asm.active])
     assert not z[~asm.active].any()
     ctx.vfs_set_preconditioner(None)
     net.close()
