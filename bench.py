@@ -185,8 +185,8 @@ def cpu_oracle_leg(baseline_case, iters, main_out, batch_out, baseline=True, che
     (DOF*iter/s on the host).
     error_vs_fp64_oracle: each 3D result in extra3d ((key, case, sites, host
     copies)) on sub-boxes (crop_errors); each 2D result in extra2d ((key,
-    case, host copies)) and the smallest batched problem (batch_out) against
-    the oracle's direct FP64 step."""
+    case, host copies)) and the batched problems in batch_out (the smallest,
+    middle and largest) against the oracle's direct FP64 step."""
     import numpy as np
     from oracle import cg, system
     res = {}
@@ -208,11 +208,10 @@ def cpu_oracle_leg(baseline_case, iters, main_out, batch_out, baseline=True, che
     for key, c2, got in extra2d:
         if check:
             res[key] = compare(c2, got)
-    if check and batch_out is not None:
-        e = compare(batch_out["case"], batch_out)
-        res["batch64_error_vs_fp64_oracle"] = {"problem": batch_out["problem"],
-                                               "n": batch_out["case"]["n"][0],
-                                               "tol": batch_out["tol"], **e}
+    if check and batch_out:
+        res["batch64_error_vs_fp64_oracle"] = [
+            {"problem": q["problem"], "n": q["case"]["n"][0], "tol": q["tol"],
+             **compare(q["case"], q)} for q in batch_out]
     if baseline and baseline_case is not None:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
@@ -270,10 +269,12 @@ def column128_leg(V):
     return out, got
 
 
-# The batched configuration leaves its tolerance unstated.  At 1e-6 the
-# smallest problem's velocity was 1.35e-4 from the FP64 oracle's (above the
-# mixed path's 1e-4 bar); 1e-7 keeps it within the bar.
-BATCH_TOL = 1e-7
+# The batched configuration leaves its tolerance unstated.  The velocity error
+# against the FP64 oracle grows with the problem's conditioning: at 1e-6 the
+# 64^2 problem was 1.35e-4 off and at 1e-7 the 320^2 one 4.2e-4, both above
+# the mixed path's 1e-4 bar; 1e-9 keeps the smallest, middle and largest
+# problems within it.
+BATCH_TOL = 1e-9
 
 
 def batch64_leg(V):
@@ -281,8 +282,8 @@ def batch64_leg(V):
     problems of sizes {64, 96, ..., 512}^2, tile shape and workgroups per CU
     picked by the autotuner, mixed precision to 1e-6.  Reports the solve time,
     aggregate DOF*iter/s and per-problem latency percentiles; returns with
-    them host copies of the smallest problem's velocity and solution for the
-    CPU leg to check."""
+    them host copies of the velocity and solution of the smallest, middle and
+    largest problems for the CPU leg to check."""
     import numpy as np
     import cases
     from paper_1010_2832_amd import autotune
@@ -311,9 +312,11 @@ def batch64_leg(V):
            "grid": st["grid"], "graph_used": bool(st["graph_used"]),
            "max_rel_residual_fp64": max(p["rel_residual"] for p in per),
            "max_iterations": st["max_iterations"]}
-    i = int(np.argmin(sizes))
-    got = {"problem": i, "case": probs[i], "tol": BATCH_TOL, "velocity": b.vfs_batch_get_velocity(i),
-           "solution": b.vfs_batch_get_solution(i)}
+    order = np.argsort(sizes, kind="stable")
+    got = []
+    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        got.append({"problem": i, "case": probs[i], "tol": BATCH_TOL,
+                    "velocity": b.vfs_batch_get_velocity(i), "solution": b.vfs_batch_get_solution(i)})
     b.close()
     return out, got
 

@@ -8,6 +8,7 @@ Paper references (section / equation labels of the paper):
     eq. stokesmixedsystemspd, in the factored form of Section 7
     ("Generalization and Further Factorization");
   * prescribed solid velocity right-hand side: Section 6.2;
+  * prescribed traction on the free surface (p_BC, tau_BC): Section 6.1;
   * null-space elimination: Section 8;
   * body force: the fractional step of Section 10 (u* = u^n + dt g).
 
@@ -25,6 +26,21 @@ tau_xx + tau_yy/2 = mu(u_x - w_z) of Section 5).  Eliminating u gives
   Dg = W_Ft W_Lt C on stresses, 0 on pressure
   b = B^T (W_F u* + W_S u_BC) - W_L W_S (B0^T u_BC),  B0 = [G | D^T]
   u = u* - dt (B x) / (rho W_L) on faces with K > 0; u_BC where W_F = 0.
+
+Prescribed traction (Section 6.1).  With boundary values y = (tau_BC, p_BC)
+given at the samples, the air-region integral of the boundary work adds
+W_F [W_A^u B0 y - B0 (W_A y)] to the right-hand side of the velocity rows
+(W_A = 1 - W_L), and every eliminated sample takes its boundary value y
+instead of 0 (Section 8), which moves -W_F B0 (W_L y) of those samples to the
+right-hand side too.  Together, with a = W_L * active,
+  f = B0 (a y) - W_L^u (B0 y)
+and eliminating u folds it into the input velocity on faces with K > 0:
+  u*_eff = u* + dt f / (rho W_L).
+Sign: the paper integrates with the normal pointing out of the air region,
+and its right-hand side taken literally turns a uniform p_BC = p0 into a
+liquid pressure shifted by -p0.  Here the work term has the sign for which a
+prescribed pressure p_BC gives liquid pressure p = p_BC at the surface (the
+uniform p0 shifts the pressure by +p0 and leaves the flow unchanged).
 """
 from __future__ import annotations
 
@@ -94,9 +110,11 @@ class Assembly:
     Dg: sp.csr_matrix          # compliance block (samples x samples), active only
     A_full: sp.csr_matrix      # dt B^T K B + Dg on all samples
     b_full: np.ndarray
-    u_star: list
+    u_star: list               # input velocity (with the traction terms folded in)
     u_bc: np.ndarray           # per face (zero on box faces)
     act_idx: np.ndarray = field(default=None)
+    u_star_in: list = field(default=None)    # u^n + dt g (before the traction terms)
+    y_bc: np.ndarray = field(default=None)   # prescribed (tau, p) per sample, or None
 
     @property
     def A(self):
@@ -144,6 +162,28 @@ def compliance(grid, wl_s, wf_s, mu_s, active):
                          shape=(n, n))
 
 
+def traction_samples(grid, case):
+    """Prescribed boundary values (tau_BC, p_BC) in sample order (Section
+    6.1), or None when the case prescribes none.  case["p_bc"]: cell array;
+    case["tau_bc"]: the stress arrays in sample order after p (tau_xx, tau_xy
+    in 2D; tau_xx, tau_yy, tau_xy, tau_xz, tau_yz in 3D), native shapes;
+    either may be absent (zero)."""
+    p_bc = case.get("p_bc")
+    tau_bc = case.get("tau_bc")
+    if p_bc is None and tau_bc is None:
+        return None
+    parts = []
+    k = 0
+    for name, st in grid.samples:
+        if name == "p":
+            src = p_bc
+        else:
+            src = None if tau_bc is None else tau_bc[k]
+            k += 1
+        parts.append(np.zeros(grid.size(st)) if src is None else grid.flat(src))
+    return np.concatenate(parts)
+
+
 def assemble(case, dt=None, w_min=1e-3):
     """Steps (a1)-(a4): body force, weights, coefficients, null-space
     elimination, A and b.  ``case`` is a dict from the ``cases`` module."""
@@ -187,8 +227,14 @@ def assemble(case, dt=None, w_min=1e-3):
     Dg = compliance(grid, wl_s, wf_s, mu_s, active)
     A_full = (dt * (B.T @ sp.diags(K) @ B) + Dg).tocsr()
 
-    u_star = body_force(case["u"], case["g"], dt)
-    us = np.concatenate([grid.flat(q) for q in u_star])
+    u_star_in = body_force(case["u"], case["g"], dt)
+    us = np.concatenate([grid.flat(q) for q in u_star_in])
+    y_bc = traction_samples(grid, case)
+    if y_bc is not None:
+        f = B0 @ (a * y_bc) - wl_f * (B0 @ y_bc)
+        us = us.copy()
+        us[kpos] += dt * f[kpos] / (rho_f[kpos] * wl_f[kpos])
+    u_star = split_faces(grid, us)
     if case.get("u_bc") is not None:
         ubc = np.concatenate([grid.flat(q) for q in case["u_bc"]])
     else:
@@ -206,10 +252,18 @@ def assemble(case, dt=None, w_min=1e-3):
     ws_f = 1.0 - wf_f
     ws_s = 1.0 - wf_s
     b_full = a * (B0.T @ (wf_f * us + ws_f * ubc) - ws_s * (B0.T @ ubc))
+    if y_bc is not None:
+        # eliminated samples hold their boundary value: in 3D the compliance
+        # couples a cell's tau_xx and tau_yy, so a fixed one moves its
+        # coupling term to the right-hand side of the other
+        fixed = y_bc * (~active)
+        coupling = compliance(grid, wl_s, wf_s, mu_s, np.ones(grid.n_samples(), dtype=bool))
+        b_full = b_full - active * (coupling @ fixed)
 
     asm = Assembly(grid=grid, dt=dt, W=W, wl_s=wl_s, wf_s=wf_s, wl_f=wl_f, wf_f=wf_f,
                    rho_f=rho_f, mu_s=mu_s, K=K, bad=bad, invalid=invalid, active=active, B0=B0, B=B,
-                   Dg=Dg, A_full=A_full, b_full=b_full, u_star=u_star, u_bc=ubc)
+                   Dg=Dg, A_full=A_full, b_full=b_full, u_star=u_star, u_bc=ubc,
+                   u_star_in=u_star_in, y_bc=y_bc)
     asm.act_idx = np.flatnonzero(active)
     return asm
 
@@ -326,7 +380,7 @@ def kkt_dense(asm):
     M[:nf, nf:] = wf[:, None] * B
     M[nf:, :nf] = (wf[:, None] * B).T
     M[nf:, nf:] = -Dg
-    us = np.concatenate([grid.flat(q) for q in asm.u_star])
+    us = np.concatenate([grid.flat(q) for q in asm.u_star_in])
     rhs = np.zeros(nf + ns)
     rhs[:nf] = m * us[fidx]
     # constraint rows: B^T W_F u = -(B^T W_S u_BC - W_L W_S B0^T u_BC) on active rows
@@ -334,5 +388,19 @@ def kkt_dense(asm):
     ws_f = 1.0 - asm.wf_f
     ws_s = 1.0 - asm.wf_s
     corr = a * (asm.B0.T @ (ws_f * asm.u_bc) - ws_s * (asm.B0.T @ asm.u_bc))
+    if asm.y_bc is not None:
+        # Section 6.1's air-region work terms and the boundary values of the
+        # eliminated samples, on the velocity rows (sign as read in the header)
+        y = asm.y_bc
+        wa_f = 1.0 - asm.wl_f
+        wa_s = 1.0 - asm.wl_s
+        fixed = asm.wl_s * (~asm.active) * y
+        t = wa_f * (asm.B0 @ y) - asm.B0 @ (wa_s * y) - asm.B0 @ fixed
+        rhs[:nf] += (asm.wf_f * t)[fidx]
+        # a fixed sample's compliance coupling (3D tau_xx / tau_yy) on the
+        # stress rows
+        coupling = compliance(grid, asm.wl_s, asm.wf_s, asm.mu_s,
+                              np.ones(grid.n_samples(), dtype=bool))
+        corr = corr - coupling @ (y * (~asm.active))
     rhs[nf:] = -corr[sidx]
     return M, rhs, fidx, sidx

@@ -152,7 +152,7 @@ def test_batch64_full_size():
     b.close()
     # parity at the tolerance the benchmark reports (bench.BATCH_TOL): a fresh
     # batch, one step, against the oracle on three problems
-    b = V.batch_from_cases(probs, tol=1e-7)
+    b = V.batch_from_cases(probs, tol=1e-9)
     b.vfs_batch_step(probs[0]["dt"])
     for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
         asm, x, u = system.step(probs[i])
