@@ -167,6 +167,20 @@ int vfs_set_velocity(vfs_ctx* ctx, const double* u, const double* v, const doubl
  * a static solid.  Values on box faces are ignored (box walls are static). */
 int vfs_set_solid_velocity(vfs_ctx* ctx, const double* ub, const double* vb, const double* wb);
 
+/* Prescribed traction on the free surface (Section 6.1), e.g. a surface-
+ * tension pressure: boundary values of the pressure and of the deviatoric
+ * stress, given as fields at their samples (p_bc: cells; tau_bc[0..1] in 2D:
+ * tau_xx cells, tau_xy nodes; tau_bc[0..4] in 3D: xx, yy cells, xy, xz, yz
+ * edges, the shapes of the conventions above).  Only their values in the air
+ * part of the control volumes near the surface and at eliminated samples
+ * matter: the air-region boundary work enters the right-hand side, and a
+ * sample removed by the null-space elimination takes its boundary value
+ * instead of 0 (Section 8).  The sign is such that a uniform p_bc = p0
+ * raises the liquid pressure by p0 and leaves the flow unchanged.  NULL
+ * pointers mean 0; p_bc and tau_bc both NULL (or every entry NULL) switch
+ * the terms off.  Applied from the next assemble/step.  EINVAL on NaN/Inf. */
+int vfs_set_traction(vfs_ctx* ctx, const double* p_bc, const double* const* tau_bc);
+
 /* Body force per unit mass, g[0..dim-1]. */
 int vfs_set_gravity(vfs_ctx* ctx, const double* g);
 

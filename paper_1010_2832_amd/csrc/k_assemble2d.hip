@@ -235,7 +235,50 @@ __global__ void k_velocity2d(Geo g, double dt, const double* __restrict__ x,
     }
 }
 
+// Prescribed traction (Section 6.1): with boundary values y = (p_BC, tau_BC)
+// per sample, the air-region boundary work and the boundary values of the
+// eliminated samples add f = B0 (a y) - W_L (B0 y) to the velocity rows; on a
+// face with K > 0 eliminating the velocity folds it into the input velocity,
+// u* += dt f / (rho W_L).  B0's stencils are those of k_velocity2d.
+__global__ void k_traction2d(Geo g, double dt, const double* __restrict__ y,
+                             const double* __restrict__ a, const double* __restrict__ rhof,
+                             const double* __restrict__ WL, const uint8_t* __restrict__ fflag,
+                             double* __restrict__ ustar) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i > g.nx || j > g.ny) return;
+    const long long NP = g.NP;
+    const long long o = g.idx(i, j);
+    const double *P = y, *X = y + NP, *Y = y + 2 * NP;
+    const double *aP = a, *aX = a + NP, *aY = a + 2 * NP;
+    const double s = dt / g.h;
+    if (j < g.ny && (fflag[o] & FK)) {
+        const long long om = g.idx(i - 1, j), oy = g.idx(i, j + 1);
+        const double day = (aP[o] * P[o] - aP[om] * P[om]) + (aX[om] * X[om] - aX[o] * X[o]) +
+                           (aY[o] * Y[o] - aY[oy] * Y[oy]);
+        const double dy = (P[o] - P[om]) + (X[om] - X[o]) + (Y[o] - Y[oy]);
+        const double wl = WL[NP + o];
+        ustar[o] += s * (day - wl * dy) / (rhof[o] * wl);
+    }
+    if (i < g.nx && (fflag[NP + o] & FK)) {
+        const long long om = g.idx(i, j - 1), ox = g.idx(i + 1, j);
+        const double day = (aP[o] * P[o] - aP[om] * P[om]) + (aX[o] * X[o] - aX[om] * X[om]) +
+                           (aY[o] * Y[o] - aY[ox] * Y[ox]);
+        const double dy = (P[o] - P[om]) + (X[o] - X[om]) + (Y[o] - Y[ox]);
+        const double wl = WL[2 * NP + o];
+        ustar[NP + o] += s * (day - wl * dy) / (rhof[NP + o] * wl);
+    }
+}
+
 }  // namespace
+
+void launch_traction2d(const Geo& g, double dt, const double* y, const double* a,
+                       const double* rhof, const double* WL, const uint8_t* fflag, double* ustar,
+                       hipStream_t s) {
+    dim3 bs(64, 4);
+    dim3 gs((g.nx + 1 + 63) / 64, (g.ny + 1 + 3) / 4);
+    hipLaunchKernelGGL(k_traction2d, gs, bs, 0, s, g, dt, y, a, rhof, WL, fflag, ustar);
+}
 
 void launch_face_coef2d(const Geo& g, double dt, const double* g3, const double* WL, double* WF,
                         const double* rho, const double* u, double* ustar, double* rhof,

@@ -286,6 +286,69 @@ __global__ void k_velocity3d(Geo g, double dt, const double* __restrict__ x,
     }
 }
 
+// Prescribed traction (Section 6.1), 3D counterpart of k_traction2d: on
+// faces with K > 0, u* += dt f / (rho W_L), f = B0 (a y) - W_L (B0 y), with
+// B0's stencils of k_velocity3d.
+__global__ void k_traction3d(Geo g, double dt, const double* __restrict__ y,
+                             const double* __restrict__ a, const double* __restrict__ rhof,
+                             const double* __restrict__ WL, const uint8_t* __restrict__ fflag,
+                             double* __restrict__ ustar) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i > g.nx || j > g.ny || k > g.nz) return;
+    const long long NP = g.NP;
+    const long long o = g.idx(i, j, k);
+    auto AY = [&](int s, long long off) { return a[s * NP + off] * y[s * NP + off]; };
+    auto Y = [&](int s, long long off) { return y[s * NP + off]; };
+    const double sc = dt / g.h;
+    if (j < g.ny && k < g.nz && (fflag[o] & FK)) {
+        const long long om = g.idx(i - 1, j, k), oy = g.idx(i, j + 1, k), oz = g.idx(i, j, k + 1);
+        const double day = (AY(0, o) - AY(0, om)) + (AY(1, om) - AY(1, o)) + (AY(3, o) - AY(3, oy)) +
+                           (AY(4, o) - AY(4, oz));
+        const double dy = (Y(0, o) - Y(0, om)) + (Y(1, om) - Y(1, o)) + (Y(3, o) - Y(3, oy)) +
+                          (Y(4, o) - Y(4, oz));
+        const double wl = WL[NP + o];
+        ustar[o] += sc * (day - wl * dy) / (rhof[o] * wl);
+    }
+    if (i < g.nx && k < g.nz && (fflag[NP + o] & FK)) {
+        const long long om = g.idx(i, j - 1, k), ox = g.idx(i + 1, j, k), oz = g.idx(i, j, k + 1);
+        const double day = (AY(0, o) - AY(0, om)) + (AY(2, om) - AY(2, o)) + (AY(3, o) - AY(3, ox)) +
+                           (AY(5, o) - AY(5, oz));
+        const double dy = (Y(0, o) - Y(0, om)) + (Y(2, om) - Y(2, o)) + (Y(3, o) - Y(3, ox)) +
+                          (Y(5, o) - Y(5, oz));
+        const double wl = WL[2 * NP + o];
+        ustar[NP + o] += sc * (day - wl * dy) / (rhof[NP + o] * wl);
+    }
+    if (i < g.nx && j < g.ny && (fflag[2 * NP + o] & FK)) {
+        const long long om = g.idx(i, j, k - 1), ox = g.idx(i + 1, j, k), oy = g.idx(i, j + 1, k);
+        const double day = (AY(0, o) - AY(0, om)) + (AY(1, o) - AY(1, om)) + (AY(2, o) - AY(2, om)) +
+                           (AY(4, o) - AY(4, ox)) + (AY(5, o) - AY(5, oy));
+        const double dy = (Y(0, o) - Y(0, om)) + (Y(1, o) - Y(1, om)) + (Y(2, o) - Y(2, om)) +
+                          (Y(4, o) - Y(4, ox)) + (Y(5, o) - Y(5, oy));
+        const double wl = WL[3 * NP + o];
+        ustar[2 * NP + o] += sc * (day - wl * dy) / (rhof[2 * NP + o] * wl);
+    }
+}
+
+// A cell whose tau_xx is active and tau_yy eliminated (or the reverse): the
+// eliminated stress holds its boundary value, and the compliance coupling
+// (1/2) W_F W_L / mu of the pair moves that value times the coupling to the
+// right-hand side of the active one.  c holds W_F W_L / mu on active stresses.
+__global__ void k_traction_pair3d(Geo g, const double* __restrict__ y,
+                                  const double* __restrict__ a, const double* __restrict__ c,
+                                  double* __restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int k = blockIdx.z * blockDim.z + threadIdx.z;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+    const long long NP = g.NP;
+    const long long o = g.idx(i, j, k);
+    const bool ax = a[NP + o] != 0.0, ay = a[2 * NP + o] != 0.0;
+    if (ax && !ay) b[NP + o] -= 0.5 * c[NP + o] * y[2 * NP + o];
+    if (ay && !ax) b[2 * NP + o] -= 0.5 * c[2 * NP + o] * y[NP + o];
+}
+
 dim3 grid3(const Geo& g, dim3 bs) {
     return dim3((g.nx + 1 + bs.x - 1) / bs.x, (g.ny + 1 + bs.y - 1) / bs.y,
                 (g.nz + 1 + bs.z - 1) / bs.z);
@@ -299,6 +362,19 @@ void launch_face_coef3d(const Geo& g, double dt, const double* g3, const double*
     FaceIn f{WL, WF, rho, u, ustar, rhof, K, fflag};
     dim3 bs(64, 2, 2);
     hipLaunchKernelGGL(k_face3d, grid3(g, bs), bs, 0, s, g, dt, g3[0], g3[1], g3[2], f);
+}
+
+void launch_traction3d(const Geo& g, double dt, const double* y, const double* a,
+                       const double* rhof, const double* WL, const uint8_t* fflag, double* ustar,
+                       hipStream_t s) {
+    dim3 bs(64, 2, 2);
+    hipLaunchKernelGGL(k_traction3d, grid3(g, bs), bs, 0, s, g, dt, y, a, rhof, WL, fflag, ustar);
+}
+
+void launch_traction_pair3d(const Geo& g, const double* y, const double* a, const double* c,
+                            double* b, hipStream_t s) {
+    dim3 bs(64, 2, 2);
+    hipLaunchKernelGGL(k_traction_pair3d, grid3(g, bs), bs, 0, s, g, y, a, c, b);
 }
 
 void launch_sample_coef3d(const Geo& g, const double* WL, const double* WF, const double* mu,

@@ -506,6 +506,23 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         launch_sample_coef3d(g, ctx->WL, ctx->WF, ctx->mu, ctx->K, ctx->fflag, ctx->ustar,
                              ctx->ubc, ctx->a, ctx->c, ctx->dinv, ctx->b, ctx->sc, s);
     }
+    if (ctx->have_traction) {
+        // the traction terms change u* on faces with K > 0; the sample pass
+        // then forms b from the new u* (a, c and D^-1 do not depend on it)
+        if (g.dim == 2)
+            launch_traction2d(g, dt, ctx->ybc, ctx->a, ctx->rhof, ctx->WL, ctx->fflag, ctx->ustar, s);
+        else
+            launch_traction3d(g, dt, ctx->ybc, ctx->a, ctx->rhof, ctx->WL, ctx->fflag, ctx->ustar, s);
+        HIPCHK(hipMemsetAsync(&ctx->sc->n_active, 0, sizeof(long long), s));
+        if (g.dim == 2) {
+            launch_sample_coef2d(g, ctx->WL, ctx->WF, ctx->mu, ctx->K, ctx->fflag, ctx->ustar,
+                                 ctx->ubc, ctx->a, ctx->c, ctx->dinv, ctx->b, ctx->sc, s);
+        } else {
+            launch_sample_coef3d(g, ctx->WL, ctx->WF, ctx->mu, ctx->K, ctx->fflag, ctx->ustar,
+                                 ctx->ubc, ctx->a, ctx->c, ctx->dinv, ctx->b, ctx->sc, s);
+            launch_traction_pair3d(g, ctx->ybc, ctx->a, ctx->c, ctx->b, s);
+        }
+    }
     if (g.dim == 2) {
         launch_tiles2d(g, ctx->a, ctx->tile_flags, ctx->tile_list, ctx->tile_count, s);
         HIPCHK(hipMemcpyAsync(ctx->tile_count_host, ctx->tile_count, sizeof(int),
@@ -657,7 +674,7 @@ int vfs_destroy(vfs_ctx* ctx) {
                     ctx->p0,    ctx->p1,    ctx->q,    ctx->z,      ctx->x32,    ctx->r32,
                     ctx->p032,  ctx->p132,  ctx->q32,  ctx->z32,    ctx->partials, ctx->counter,
                     ctx->sc,    ctx->flag,  ctx->stage, ctx->netvec, ctx->netpart, ctx->netcoef,
-                    ctx->f32b,  ctx->fpart};
+                    ctx->f32b,  ctx->fpart, ctx->ybc};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->net_owned) (void)vfs_unet_destroy(ctx->net_owned);
@@ -861,6 +878,37 @@ int vfs_set_solid_velocity(vfs_ctx* ctx, const double* ub, const double* vb, con
     launch_zero_box_faces(ctx->g, ctx->ubc, ctx->stream);
     HIPCHK(hipGetLastError());
     ctx->assembled = false;
+    return VFS_OK;
+}
+
+int vfs_set_traction(vfs_ctx* ctx, const double* p_bc, const double* const* tau_bc) {
+    if (!ctx) return VFS_EINVAL;
+    const Geo& g = ctx->g;
+    bool any = p_bc != nullptr;
+    for (int s = 1; tau_bc && s < g.nsamp(); ++s) any = any || tau_bc[s - 1] != nullptr;
+    ctx->assembled = false;
+    if (!any) {
+        ctx->have_traction = false;
+        return VFS_OK;
+    }
+    if (!ctx->ybc) {
+        int rc = dalloc(ctx, &ctx->ybc, (long long)g.nsamp() * g.NP);
+        if (rc) return rc;
+    }
+    ctx->have_traction = false;
+    for (int s = 0; s < g.nsamp(); ++s) {
+        const double* src = s == 0 ? p_bc : (tau_bc ? tau_bc[s - 1] : nullptr);
+        double* dst = ctx->ybc + s * g.NP;
+        if (!src) {
+            HIPCHK(hipMemsetAsync(dst, 0, (size_t)g.NP * sizeof(double), ctx->stream));
+            continue;
+        }
+        int rc = put_set(ctx, sample_set(g.dim, s), src, dst, 0,
+                         s == 0 ? "prescribed pressure" : "prescribed stress");
+        if (rc) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    ctx->have_traction = true;
     return VFS_OK;
 }
 

@@ -171,6 +171,8 @@ struct vfs_ctx {
     double* mu = nullptr;        // padded cells
     double* u = nullptr;         // padded faces, dim slices (u^n, then u^{n+1})
     double* ubc = nullptr;       // padded faces, dim slices
+    double* ybc = nullptr;       // padded samples: prescribed (p, tau) on the free surface
+    bool have_traction = false;
 
     // assembly (device)
     double* thL = nullptr;       // compact sub-cell liquid fractions (2n)^d
@@ -279,6 +281,17 @@ void launch_velocity3d(const Geo& g, double dt, const double* x, const double* a
                        const double* ustar, const double* ubc, const double* rhof,
                        const double* WL, const double* WF, const uint8_t* fflag, double* u,
                        hipStream_t s);
+
+// prescribed traction (Section 6.1): u* on faces with K > 0 and, in 3D, the
+// coupling of an eliminated tau_xx / tau_yy on the right-hand side
+void launch_traction2d(const Geo& g, double dt, const double* y, const double* a,
+                       const double* rhof, const double* WL, const uint8_t* fflag, double* ustar,
+                       hipStream_t s);
+void launch_traction3d(const Geo& g, double dt, const double* y, const double* a,
+                       const double* rhof, const double* WL, const uint8_t* fflag, double* ustar,
+                       hipStream_t s);
+void launch_traction_pair3d(const Geo& g, const double* y, const double* a, const double* c,
+                            double* b, hipStream_t s);
 
 // packing and checks (k_util.hip)
 void launch_pack(const Geo& g, const int shp[3], const double* src, double* dst, hipStream_t s);

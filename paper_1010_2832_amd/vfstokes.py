@@ -95,6 +95,7 @@ _SIGS = {
     "vfs_set_velocity": ([_P, _P, _P, _P], _I),
     "vfs_set_solid_velocity": ([_P, _P, _P, _P], _I),
     "vfs_set_gravity": ([_P, _P], _I),
+    "vfs_set_traction": ([_P, _P, _P], _I),
     "vfs_set_solver": ([_P, _I, _I, _D, _I, _D], _I),
     "vfs_step": ([_P, _D], _I),
     "vfs_assemble": ([_P, _D], _I),
@@ -320,6 +321,20 @@ class Context:
         arr = (ctypes.c_double * 3)(*((list(g) + [0.0] * 3)[:3]))
         return _check(self.handle, _lib.vfs_set_gravity(self.handle, ctypes.cast(arr, _P)))
 
+    def vfs_set_traction(self, p_bc=None, tau_bc=None):
+        """Prescribed pressure (cells) and deviatoric stresses (list in sample
+        order after p, native shapes; None entries mean 0)."""
+        k = _Keep()
+        shapes = self.sample_shapes()
+        pp = k.ptr(p_bc, int(np.prod(shapes[0]))) if p_bc is not None else None
+        arr = None
+        if tau_bc is not None:
+            ptrs = [k.ptr(t, int(np.prod(shapes[q + 1]))) if t is not None else None
+                    for q, t in enumerate(tau_bc)]
+            arr = (_P * len(ptrs))(*ptrs)
+        return _check(self.handle, _lib.vfs_set_traction(self.handle, pp,
+                                                         ctypes.cast(arr, _P) if arr is not None else None))
+
     def vfs_set_solver(self, precond=VFS_PRECOND_JACOBI, precision=VFS_FP64, rel_tol=1e-6,
                        max_iter=100000, w_min=1e-3):
         rc = _check(self.handle, _lib.vfs_set_solver(self.handle, precond, precision, rel_tol,
@@ -453,6 +468,8 @@ def context_from_case(case, precision=VFS_FP64, tol=None, max_iter=200000, w_min
     ctx.vfs_set_velocity(case["u"])
     ctx.vfs_set_solid_velocity(case.get("u_bc"))
     ctx.vfs_set_gravity(case["g"])
+    if case.get("p_bc") is not None or case.get("tau_bc") is not None:
+        ctx.vfs_set_traction(case.get("p_bc"), case.get("tau_bc"))
     ctx.vfs_set_solver(VFS_PRECOND_JACOBI, precision, tol if tol is not None else case.get("tol", 1e-6),
                        max_iter, w_min)
     return ctx
