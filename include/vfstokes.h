@@ -181,6 +181,26 @@ int vfs_set_solid_velocity(vfs_ctx* ctx, const double* ub, const double* vb, con
  * the terms off.  Applied from the next assemble/step.  EINVAL on NaN/Inf. */
 int vfs_set_traction(vfs_ctx* ctx, const double* p_bc, const double* const* tau_bc);
 
+/* Advection half of the fractional step of Section 10, to call before
+ * vfs_step: first-order semi-Lagrangian advection (bilinear in 2D, trilinear
+ * in 3D) of the context's velocity and of its liquid level set, FP64.  The
+ * velocity the last vfs_step defined (faces with K > 0, and solid or box
+ * faces, W_F = 0) is first extended three face layers into the air, each
+ * unknown face taking the mean of its known same-component neighbours; a
+ * velocity given by vfs_set_velocity counts as known everywhere.  Each face
+ * value (and each level-set node) becomes the interpolant of the extended
+ * field at its departure point x - dt v(x), clamped to the box.  The solid
+ * level set and solid velocity are unchanged.  Allocates its work buffers on
+ * the first call.  ESTATE before velocity and level sets are set. */
+int vfs_advect(vfs_ctx* ctx, double dt);
+/* The current liquid level set (after vfs_advect), nodal shape. */
+int vfs_get_level_set(vfs_ctx* ctx, double* phi_liquid);
+/* Warm start (1) or not (0, default): the VFS_MIXED solve of vfs_step starts
+ * from the previous step's solution on the samples that are still active,
+ * instead of 0; the tolerance stays relative to |b|.  FP64 solves and
+ * vfs_solve always start from 0. */
+int vfs_set_warm_start(vfs_ctx* ctx, int on);
+
 /* Body force per unit mass, g[0..dim-1]. */
 int vfs_set_gravity(vfs_ctx* ctx, const double* g);
 

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <utility>
 
 #include "vfs_internal.h"
 #include "vfs_unet.h"
@@ -411,14 +412,26 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
         if (int rc0 = net_prepare_ctx(ctx->net, ctx)) return fail(ctx, rc0, ctx->net->err);
     }
     int fallbacks = 0;
+    // warm start: keep the last solution on the samples that are still active
+    const bool warm = ctx->warm_start && ctx->have_x && x == ctx->x;
+    if (warm)
+        HIPCHK(hipMemcpyAsync(ctx->z, x, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice,
+                              ctx->stream));
     HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), ctx->stream));
     Scalars so{};
     int rc = true_residual(ctx, b, x, &so);
     if (rc) return rc;
     const double bnorm = std::sqrt(so.aux0);
     double rho = bnorm;
+    if (warm && bnorm > 0.0) {
+        launch_mask(x, ctx->z, ctx->a, n, ctx->stream);
+        HIPCHK(hipGetLastError());
+        rc = true_residual(ctx, b, x, &so);
+        if (rc) return rc;
+        rho = std::sqrt(so.aux0);
+    }
     int total = 0, outer = 0, status = VFS_OK, stalls = 0;
-    double rel = bnorm > 0 ? 1.0 : 0.0;
+    double rel = bnorm > 0 ? rho / bnorm : 0.0;
     while (bnorm > 0.0) {
         rel = rho / bnorm;
         if (rel <= ctx->tol) break;
@@ -674,7 +687,8 @@ int vfs_destroy(vfs_ctx* ctx) {
                     ctx->p0,    ctx->p1,    ctx->q,    ctx->z,      ctx->x32,    ctx->r32,
                     ctx->p032,  ctx->p132,  ctx->q32,  ctx->z32,    ctx->partials, ctx->counter,
                     ctx->sc,    ctx->flag,  ctx->stage, ctx->netvec, ctx->netpart, ctx->netcoef,
-                    ctx->f32b,  ctx->fpart, ctx->ybc};
+                    ctx->f32b,  ctx->fpart, ctx->ybc, ctx->adv_a, ctx->adv_b, ctx->adv_ka,
+                    ctx->adv_kb, ctx->phi_tmp};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->net_owned) (void)vfs_unet_destroy(ctx->net_owned);
@@ -859,6 +873,7 @@ int vfs_set_velocity(vfs_ctx* ctx, const double* u, const double* v, const doubl
         if (rc) return rc;
     }
     ctx->have_u = true;
+    ctx->u_from_step = false;
     ctx->assembled = false;
     return VFS_OK;
 }
@@ -909,6 +924,52 @@ int vfs_set_traction(vfs_ctx* ctx, const double* p_bc, const double* const* tau_
     }
     HIPCHK(hipGetLastError());
     ctx->have_traction = true;
+    return VFS_OK;
+}
+
+int vfs_advect(vfs_ctx* ctx, double dt) {
+    if (!ctx) return VFS_EINVAL;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, VFS_EINVAL, "dt must be > 0 and finite");
+    if (!ctx->have_u || !ctx->have_phi)
+        return fail(ctx, VFS_ESTATE, "velocity and level sets must be set");
+    const Geo& g = ctx->g;
+    const long long nf = (long long)g.dim * g.NP;
+    if (!ctx->adv_a) {
+        int rc = dalloc(ctx, &ctx->adv_a, nf);
+        if (!rc) rc = dalloc(ctx, &ctx->adv_b, nf);
+        if (!rc) rc = dalloc(ctx, &ctx->adv_ka, nf);
+        if (!rc) rc = dalloc(ctx, &ctx->adv_kb, nf);
+        if (!rc) rc = dalloc(ctx, &ctx->phi_tmp, node_count(g));
+        if (rc) return rc;
+    }
+    hipStream_t s = ctx->stream;
+    // faces the last Stokes step defined; every face when the velocity came
+    // from the caller (or from a previous advection)
+    const bool all = !(ctx->u_from_step && ctx->assembled);
+    launch_known_faces(g, ctx->fflag, ctx->WF, all, ctx->adv_kb, s);
+    launch_extend(g, ctx->u, ctx->adv_kb, ctx->adv_a, ctx->adv_ka, s);
+    launch_extend(g, ctx->adv_a, ctx->adv_ka, ctx->adv_b, ctx->adv_kb, s);
+    launch_extend(g, ctx->adv_b, ctx->adv_kb, ctx->adv_a, ctx->adv_ka, s);
+    launch_advect_u(g, dt, ctx->adv_a, ctx->u, s);
+    launch_advect_phi(g, dt, ctx->adv_a, ctx->phi_l, ctx->phi_tmp, s);
+    HIPCHK(hipGetLastError());
+    std::swap(ctx->phi_l, ctx->phi_tmp);
+    ctx->u_from_step = false;
+    ctx->assembled = false;
+    return VFS_OK;
+}
+
+int vfs_get_level_set(vfs_ctx* ctx, double* phi_liquid) {
+    if (!ctx || !phi_liquid) return ctx ? fail(ctx, VFS_EINVAL, "NULL output") : VFS_EINVAL;
+    HIPCHK(hipMemcpyAsync(phi_liquid, ctx->phi_l, (size_t)node_count(ctx->g) * sizeof(double),
+                          hipMemcpyDefault, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return VFS_OK;
+}
+
+int vfs_set_warm_start(vfs_ctx* ctx, int on) {
+    if (!ctx) return VFS_EINVAL;
+    ctx->warm_start = on != 0;
     return VFS_OK;
 }
 
@@ -971,6 +1032,8 @@ int vfs_step(vfs_ctx* ctx, double dt) {
     HIPCHK(hipEventRecord(ctx->ev[2], s));
     rc = recover_internal(ctx);
     if (rc) return rc;
+    ctx->u_from_step = true;
+    ctx->have_x = true;
     HIPCHK(hipEventRecord(ctx->ev[3], s));
     HIPCHK(hipEventSynchronize(ctx->ev[3]));
     ctx->stats.t_assemble_ms = elapsed(ctx->ev[0], ctx->ev[1]);
@@ -1001,6 +1064,7 @@ int vfs_solve(vfs_ctx* ctx, const double* b, double* x) {
     if (!ctx->assembled) return fail(ctx, VFS_ESTATE, "call vfs_assemble first");
     int rc = pack_samples(ctx, b, ctx->z);
     if (rc) return rc;
+    ctx->have_x = false;   // a raw solve starts from 0
     launch_mask(ctx->b, ctx->z, ctx->a, (long long)ctx->g.nsamp() * ctx->g.NP, ctx->stream);
     HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
     const int status = solve_internal(ctx, ctx->b, ctx->x);

@@ -174,6 +174,17 @@ struct vfs_ctx {
     double* ybc = nullptr;       // padded samples: prescribed (p, tau) on the free surface
     bool have_traction = false;
 
+    // fractional step (vfs_advect): extension buffers, known-face flags and
+    // the advected level set; u_from_step: ctx->u is the last step's velocity
+    double* adv_a = nullptr;
+    double* adv_b = nullptr;
+    uint8_t* adv_ka = nullptr;
+    uint8_t* adv_kb = nullptr;
+    double* phi_tmp = nullptr;
+    bool u_from_step = false;
+    bool warm_start = false;     // mixed solves start from the last solution
+    bool have_x = false;         // ctx->x holds a solution of the last step
+
     // assembly (device)
     double* thL = nullptr;       // compact sub-cell liquid fractions (2n)^d
     double* thF = nullptr;       // compact sub-cell fluid fractions
@@ -292,6 +303,15 @@ void launch_traction3d(const Geo& g, double dt, const double* y, const double* a
                        hipStream_t s);
 void launch_traction_pair3d(const Geo& g, const double* y, const double* a, const double* c,
                             double* b, hipStream_t s);
+
+// fractional step (k_advect.hip)
+void launch_known_faces(const Geo& g, const uint8_t* fflag, const double* WF, bool all,
+                        uint8_t* known, hipStream_t s);
+void launch_extend(const Geo& g, const double* vin, const uint8_t* kin, double* vout,
+                   uint8_t* kout, hipStream_t s);
+void launch_advect_u(const Geo& g, double dt, const double* uext, double* uout, hipStream_t s);
+void launch_advect_phi(const Geo& g, double dt, const double* uext, const double* phi, double* out,
+                       hipStream_t s);
 
 // packing and checks (k_util.hip)
 void launch_pack(const Geo& g, const int shp[3], const double* src, double* dst, hipStream_t s);

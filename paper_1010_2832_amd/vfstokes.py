@@ -96,6 +96,9 @@ _SIGS = {
     "vfs_set_solid_velocity": ([_P, _P, _P, _P], _I),
     "vfs_set_gravity": ([_P, _P], _I),
     "vfs_set_traction": ([_P, _P, _P], _I),
+    "vfs_advect": ([_P, _D], _I),
+    "vfs_get_level_set": ([_P, _P], _I),
+    "vfs_set_warm_start": ([_P, _I], _I),
     "vfs_set_solver": ([_P, _I, _I, _D, _I, _D], _I),
     "vfs_step": ([_P, _D], _I),
     "vfs_assemble": ([_P, _D], _I),
@@ -334,6 +337,17 @@ class Context:
             arr = (_P * len(ptrs))(*ptrs)
         return _check(self.handle, _lib.vfs_set_traction(self.handle, pp,
                                                          ctypes.cast(arr, _P) if arr is not None else None))
+
+    def vfs_advect(self, dt):
+        return _check(self.handle, _lib.vfs_advect(self.handle, dt))
+
+    def vfs_get_level_set(self):
+        out = np.zeros(int(np.prod([q + 1 for q in self.n])))
+        _check(self.handle, _lib.vfs_get_level_set(self.handle, out.ctypes.data))
+        return out.reshape(tuple(q + 1 for q in self.n), order="F")
+
+    def vfs_set_warm_start(self, on=True):
+        return _check(self.handle, _lib.vfs_set_warm_start(self.handle, 1 if on else 0))
 
     def vfs_set_solver(self, precond=VFS_PRECOND_JACOBI, precision=VFS_FP64, rel_tol=1e-6,
                        max_iter=100000, w_min=1e-3):
