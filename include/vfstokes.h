@@ -256,6 +256,27 @@ int vfs_set_profiling(vfs_ctx* ctx, int on);
 /* Number of entries of a sample-order vector and of the face vector. */
 int vfs_get_sizes(const vfs_ctx* ctx, int64_t* n_samples, int64_t* n_faces);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the liquid
+ * volume fractions W_L of one sample set (VFS_SET_*) computed straight from a
+ * nodal liquid level set, without a context, allocating nothing.  The result
+ * is bit-identical to vfs_get_weights(ctx, set, VFS_WEIGHT_LIQUID, out) on a
+ * context assembled from the same level set and w_min (W_L ignores solids).
+ *   phi_liquid: DEVICE memory, (nx+1) x (ny+1) [x (nz+1)] FP64, x-fastest.
+ *   out:        DEVICE memory, the set's native shape (see the conventions).
+ * Work is queued on hip_stream (NULL = the null stream) and the call returns
+ * without synchronising; NaN/Inf in phi_liquid are not checked.  The work
+ * space is one fixed 96 MiB device array per GPU, held until the process
+ * ends: it takes (16 (nx ny [nz]) + 2 nsets NP) doubles, NP the padded grid
+ * size of the conventions above, which admits square 2D grids up to 882^2
+ * and cubic 3D grids up to 72^3; larger grids return VFS_EINVAL.  Every call on a
+ * GPU shares that GPU's array, so calls that overlap in time on one GPU
+ * (different streams or threads) race and must be serialised by the caller.
+ * Errors: VFS_EINVAL (sizes, set, w_min, NULL pointers), VFS_EHIP; the
+ * message is vfs_last_error(NULL). */
+int vfs_liquid_weights_noalloc(int dim, int nx, int ny, int nz, double w_min,
+                               const double* phi_liquid, int set, double* out, void* hip_stream);
+
 /* ------------------------------------------------------------------------
  * Batched 2D steps: many independent problems of different sizes.  All
  * their solves run in one persistent launch (FP32 Jacobi PCG with FP64

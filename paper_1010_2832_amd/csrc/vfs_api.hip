@@ -631,6 +631,7 @@ int ctx_get_samples(vfs_ctx* ctx, const double* src, double* user) {
     return unpack_samples(ctx, src, user);
 }
 int ctx_fail(vfs_ctx* ctx, int code, const std::string& msg) { return fail(ctx, code, msg); }
+int fail_global(int code, const std::string& msg) { return fail(nullptr, code, msg); }
 
 Geo make_geo(int dim, int nx, int ny, int nz, double h) {
     Geo g{};

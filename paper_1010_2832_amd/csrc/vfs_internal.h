@@ -261,6 +261,9 @@ struct vfs_ctx {
 
 namespace vfs {
 
+// error message of a call without a context (read by vfs_last_error(NULL))
+int fail_global(int code, const std::string& msg);
+
 // ---- launchers (defined in the .hip files) ----
 // fractions / weights (k_fractions.hip)
 void launch_subcell_fractions(const Geo& g, const double* phi, double* theta, bool complement,

@@ -148,6 +148,7 @@ _SIGS = {
     "vfs_unet_train_step": ([_P, _P, _P, _P, ctypes.POINTER(_D)], _I),
     "vfs_set_preconditioner": ([_P, _P], _I),
     "vfs_load_preconditioner": ([_P, _P, ctypes.c_size_t], _I),
+    "vfs_liquid_weights_noalloc": ([_I, _I, _I, _I, _D, _P, _I, _P, _P], _I),
     "vfs_precond_apply": ([_P, _P, _P], _I),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -243,6 +244,23 @@ def vfs_create(dim, nx, ny, nz, h, origin=None):
 
 def vfs_destroy(ctx):
     return _lib.vfs_destroy(ctx)
+
+
+def vfs_liquid_weights_noalloc(dim, n, w_min, phi_liquid, set_id, out, stream_ptr=None):
+    """W_L of one sample set from a nodal liquid level set, allocating nothing.
+    phi_liquid and out are contiguous torch float64 tensors on the GPU (the
+    level set flattened x-fastest, out sized for the set); work is queued on
+    stream_ptr and not synchronised."""
+    nx, ny = int(n[0]), int(n[1])
+    nz = int(n[2]) if dim == 3 else 1
+    for t in (phi_liquid, out):
+        if not _is_torch(t) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("phi_liquid and out must be contiguous torch tensors on the GPU")
+    rc = _lib.vfs_liquid_weights_noalloc(dim, nx, ny, nz, float(w_min), phi_liquid.data_ptr(),
+                                         int(set_id), out.data_ptr(), stream_ptr)
+    if rc != VFS_OK:
+        raise VfsError(rc, _lib.vfs_last_error(None).decode())
+    return rc
 
 
 def vfs_set_stream(ctx, stream_ptr):

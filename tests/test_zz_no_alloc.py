@@ -70,6 +70,7 @@ def test_noalloc_rejects_grids_beyond_its_work_space():
     with pytest.raises(V.VfsError) as ei:
         V.vfs_liquid_weights_noalloc(3, (80, 80, 80), 1e-3, phi, 0, out)
     assert ei.value.code == V.VFS_EINVAL and "work space" in str(ei.value)
-    with pytest.raises(V.VfsError) as ei:
-        V.vfs_liquid_weights_noalloc(2, (8, 8), 1e-3, phi, 7, out)
-    assert ei.value.code == V.VFS_EINVAL
+    for bad_set in (3, 7, -1):      # 2D has cells, x and y faces and nodes (VFS_SET_NODE)
+        with pytest.raises(V.VfsError) as ei:
+            V.vfs_liquid_weights_noalloc(2, (8, 8), 1e-3, phi, bad_set, out)
+        assert ei.value.code == V.VFS_EINVAL
