@@ -22,6 +22,8 @@ Workloads (one base seed each, recorded by the caller):
   batch64    64 independent 2D problems, n in {64,96,...,512}, each shaped as
              drop32 with its own seed.
   pool256    3D 256^3 analogue of pool512 (pool + 8 spheres + moving sphere).
+  sphere_core3d  liquid sphere with a static solid core (3D convergence study).
+  jet2d, jet3d   viscous jets from a moving nozzle (fractional-step demos).
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ import numpy as np
 __all__ = [
     "node_coords", "face_coords", "cell_coords",
     "drop32", "pool512", "column128", "batch64", "pool256",
-    "drop2d", "pool2d", "pool3d", "column3d",
+    "drop2d", "pool2d", "pool3d", "column3d", "sphere_core3d", "jet2d", "jet3d",
 ]
 
 
@@ -275,3 +277,89 @@ def crop(case, lo, m):
                  np.array(np.asarray(case["mu"])[cell]), faces(case["u"]),
                  None if case["u_bc"] is None else faces(case["u_bc"]), case["g"],
                  name=f"{case.get('name', 'case')}_crop{lo}+{m}")
+
+
+# --------------------------------------------------------------------------
+# 3D sphere with a solid core (the three-dimensional convergence study)
+# --------------------------------------------------------------------------
+def sphere_core3d(n, half=1.2, radius=1.0, core=0.25, mu=0.1, rho=1.0, dt=1.0):
+    """A liquid sphere of the given radius centred at the origin with a free
+    surface, a static solid sphere of radius `core` at its centre, one step
+    from the input velocity
+        (0.5 + x sin(yz), cos(y/4) + xyz/2, x + yz^2/2 + sqrt(2 + y^2)),
+    no gravity; box [-half, half]^3 with n cells per axis (its walls, static
+    solids, do not touch the liquid when half > radius)."""
+    h = 2.0 * half / n
+    nn = (n, n, n)
+    o = (-half, -half, -half)
+    X, Y, Z = node_coords(nn, h, o)
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    phi_l = r - radius
+    phi_s = r - core
+    del X, Y, Z, r
+    fns = (lambda x, y, z: 0.5 + x * np.sin(y * z),
+           lambda x, y, z: np.cos(0.25 * y) + 0.5 * x * y * z,
+           lambda x, y, z: x + 0.5 * y * z * z + np.sqrt(2.0 + y * y))
+    u = []
+    for a in range(3):
+        F = face_coords(nn, h, o, a)
+        u.append(fns[a](*F))
+        del F
+    return _case(3, nn, h, o, dt, phi_l, phi_s, np.full(nn, rho), np.full(nn, mu), u, None,
+                 (0.0, 0.0, 0.0), name=f"sphere_core3d_{n}")
+
+
+# --------------------------------------------------------------------------
+# viscous jet buckling (the application of the fractional step)
+# --------------------------------------------------------------------------
+def jet2d(n=150, dt=2e-3, mu=0.075, rho=1.0, speed=0.5, width=0.06, ceiling=0.8,
+          radius=0.4, g=(0.0, -9.81)):
+    """2D planar jet: a disc-shaped container of the given radius around
+    (0.5, 0.5) (solid outside), a solid ceiling above y = ceiling whose part
+    over |x - 0.5| < width/2 (the nozzle) moves down at `speed`, and a short
+    liquid column under the nozzle.  `jet_seed` is the liquid level set the
+    nozzle keeps filled (the caller takes the minimum with it each step)."""
+    h = 1.0 / n
+    nn = (n, n)
+    X, Y = node_coords(nn, h, (0.0, 0.0))
+    phi_s = np.minimum(radius - np.hypot(X - 0.5, Y - 0.5), ceiling - Y)
+    seed = np.maximum(np.abs(X - 0.5) - 0.5 * width, ceiling - 2.0 * h - Y)
+    phi_l = np.maximum(np.abs(X - 0.5) - 0.5 * width, ceiling - 0.05 - Y)
+    u_bc = []
+    for a in range(2):
+        F = face_coords(nn, h, (0.0, 0.0), a)
+        inside = (np.abs(F[0] - 0.5) < 0.5 * width) & (F[1] > ceiling - 2.0 * h)
+        u_bc.append(np.where(inside, -speed if a == 1 else 0.0, 0.0))
+    u = [np.where(q != 0.0, q, 0.0) for q in u_bc]
+    c = _case(2, nn, h, (0.0, 0.0), dt, phi_l, phi_s, np.full(nn, rho), np.full(nn, mu), u, u_bc, g,
+              name=f"jet2d_{n}")
+    c["jet_seed"] = seed
+    return c
+
+
+def jet3d(n=80, dt=2e-3, mu=0.3, rho=1.0, speed=0.5, diameter=0.08, ceiling=0.8,
+          radius=0.4, g=(0.0, -9.81, 0.0)):
+    """3D cylindrical jet: a spherical container of the given radius around
+    (0.5, 0.5, 0.5) (solid outside), a solid ceiling above y = ceiling whose
+    part over the inlet disc of the given diameter around x = z = 0.5 moves
+    down at `speed`, and a short liquid column under the inlet; `jet_seed` as
+    in jet2d."""
+    h = 1.0 / n
+    nn = (n, n, n)
+    X, Y, Z = node_coords(nn, h, (0.0, 0.0, 0.0))
+    rr = np.hypot(X - 0.5, Z - 0.5)
+    phi_s = np.minimum(radius - np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 0.5) ** 2),
+                       ceiling - Y)
+    seed = np.maximum(rr - 0.5 * diameter, ceiling - 2.0 * h - Y)
+    phi_l = np.maximum(rr - 0.5 * diameter, ceiling - 0.05 - Y)
+    del X, Y, Z, rr
+    u_bc = []
+    for a in range(3):
+        F = face_coords(nn, h, (0.0, 0.0, 0.0), a)
+        inside = (np.hypot(F[0] - 0.5, F[2] - 0.5) < 0.5 * diameter) & (F[1] > ceiling - 2.0 * h)
+        u_bc.append(np.where(inside, -speed if a == 1 else 0.0, 0.0))
+    u = [q.copy() for q in u_bc]
+    c = _case(3, nn, h, (0.0, 0.0, 0.0), dt, phi_l, phi_s, np.full(nn, rho), np.full(nn, mu), u,
+              u_bc, g, name=f"jet3d_{n}")
+    c["jet_seed"] = seed
+    return c
