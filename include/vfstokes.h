@@ -130,6 +130,9 @@ typedef struct vfs_stats {
        Set by assembly.  In 2D it describes the VFS_MIXED (fused) solve; the
        2D VFS_FP64 kernels sweep the whole grid. */
     int64_t n_tile_samples;
+    /* ||b - A x0|| / ||b|| of the last solve's starting iterate x0 (1 from
+       zero; below 1 when warm-started, vfs_set_warm_start) */
+    double  rel_residual_start;
 } vfs_stats;
 
 /* Last error message of a context (or of the failed create when ctx is NULL). */

@@ -363,6 +363,7 @@ int solve_fp64(vfs_ctx* ctx, const double* b, double* x) {
     if (rc) return rc;
     int total = s.iter, outer = 0, status = VFS_OK;
     const double bb = s.bb;
+    ctx->stats.rel_residual_start = bb > 0.0 ? 1.0 : 0.0;
     const double bnorm = std::sqrt(bb);
     double rel = 0.0;
     while (bb > 0.0) {
@@ -432,6 +433,7 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
     }
     int total = 0, outer = 0, status = VFS_OK, stalls = 0;
     double rel = bnorm > 0 ? rho / bnorm : 0.0;
+    ctx->stats.rel_residual_start = rel;
     while (bnorm > 0.0) {
         rel = rho / bnorm;
         if (rel <= ctx->tol) break;

@@ -41,7 +41,8 @@ class vfs_stats(ctypes.Structure):
                 ("t_apply_avg_ms", ctypes.c_double), ("t_update_avg_ms", ctypes.c_double),
                 ("n_apply_timed", ctypes.c_int64), ("n_update_timed", ctypes.c_int64),
                 ("t_precond_avg_ms", ctypes.c_double), ("precond_fallbacks", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("n_tile_samples", ctypes.c_int64)]
+                ("pad0", ctypes.c_int32), ("n_tile_samples", ctypes.c_int64),
+                ("rel_residual_start", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}

@@ -9,10 +9,10 @@ weights, every stored activation and activation gradient); they differ in
 accumulation (FP32 on the GPU, FP64 in the oracle) and hence occasionally in
 the rounding of one stored value by one bfloat16 unit (2^-8 relative), which
 propagates.  Outputs and gradients are compared element by element: every
-entry must lie within FLIP_WORST of the tensor's largest magnitude (per
-layer for weight gradients, per output channel for the network output), and
-at most a fraction FLIP_FRAC of the entries (and never more than a handful
-in a small tensor) may differ by more than FLIP_FAR, four bfloat16 units at
+entry must lie within FLIP_WORST of the largest magnitude of its group (per
+output channel, for the network output and each layer's weight gradient),
+and at most a fraction FLIP_FRAC of the entries (never more than a handful
+in a small tensor) may differ by more than FLIP_FAR, one bfloat16 unit at
 that magnitude; the rest agree to FP32 accumulation order.  Adam is held to
 1e-6 relative (FP32 arithmetic)."""
 import numpy as np
@@ -43,9 +43,12 @@ def L():
     return learned
 
 
-FLIP_FAR = 2.0 ** -6      # four bfloat16 units at the tensor's largest magnitude
-FLIP_FRAC = 2e-3          # share of entries allowed beyond FLIP_FAR (rounding flips)
-FLIP_WORST = 2.0 ** -3    # no entry may be further off than this
+# Measured on MI355X: no entry of any compared tensor beyond one bfloat16 unit
+# at the tensor's scale; worst entries 7.0e-4 (network output, ragged 8x24x16),
+# 3.5e-4 (a weight gradient), 6.5e-8 (preconditioner application).
+FLIP_FAR = 2.0 ** -8      # one bfloat16 unit at the tensor's largest magnitude
+FLIP_FRAC = 1e-3          # share of entries allowed beyond FLIP_FAR (rounding flips)
+FLIP_WORST = 2.0 ** -6    # no entry may be further off than this (22x the worst seen)
 
 
 def _flip_check(tag, got, ref, groups=None):
