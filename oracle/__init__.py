@@ -19,9 +19,15 @@ Time-Dependent, Variable Coefficient Stokes Flow on Irregular Domains"):
                 and its right-hand side (eq. stokesmixedsystemspd and the
                 prescribed-velocity terms of Section 6), direct and CG
                 solves, velocity recovery, and the full (u, tau, p) KKT
-                system (eq. stokesmixedsystem) for cross-checks
+                system (eq. stokesmixedsystem) for cross-checks; the
+                prescribed-traction terms of Section 6.1
   cg.py         plain Jacobi-preconditioned CG (the CPU timing baseline)
+  advect.py     the fractional step of Section 10: semi-Lagrangian velocity
+                and level-set advection around the Stokes step
+  schwarz.py    brick-local additive Schwarz / block symmetric Gauss-Seidel
+                preconditioners and textbook PCG with them
+  learned.py    the learned preconditioner's network, loss and flexible CG
 
 Every function is FP64 and unoptimised on purpose.
 """
-from . import grid, fractions, operators, system, cg  # noqa: F401
+from . import grid, fractions, operators, system, cg, advect, schwarz  # noqa: F401

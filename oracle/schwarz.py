@@ -1,0 +1,124 @@
+"""Brick-local Schwarz preconditioners for the SPD system (test
+infrastructure only; plain NumPy/SciPy).
+
+The paper solves its SPD system with CG preconditioned by an overlapping
+multiplicative Schwarz domain decomposition built from a graph partition
+(Section 7's closing paragraph, Section 9's opening paragraph).  The
+preconditioners here are additive, on a geometric partition, with an
+inexact local solver -- the form whose subdomains can be solved
+independently -- and are defined as follows.
+
+  * Anchors: a sample of any type at array index (i, j[, k]) is anchored at
+    that index; anchors run over 0..n per axis.  Bricks of b anchors per
+    axis partition the anchors; brick I covers [I b, I b + b).  Its
+    extended brick adds `overlap` anchors on each side (clipped to 0..n).
+    Subdomain I = the active samples anchored in the extended brick.
+  * Colours: (sample type q, parity of i + j [+ k]).  Two samples of one
+    colour never share a face, so A has no entry between them and a colour
+    can be relaxed all at once.  Order: q = 0, 1, ..., parity 0 before 1.
+  * Local solver G_I: one symmetric Gauss-Seidel sweep on A_I, the
+    principal submatrix of A on subdomain I, from zero -- every colour in
+    order, then every colour in reverse order, each sample updated by
+    x_s += (r_s - (A_I x)_s) / A_ss.  G_I = (D + U)^-1 D (D + L)^-1 in the
+    colour ordering, symmetric positive definite.
+  * Preconditioner: z = sum_I R_I^T G_I R_I r (additive Schwarz; with
+    overlap 0 the subdomains are disjoint: block symmetric Gauss-Seidel).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def anchors(grid):
+    """Per sample (sample order): its anchor index (array of shape
+    (n_samples, d)) and its sample type."""
+    idx, typ = [], []
+    for q, (name, st) in enumerate(grid.samples):
+        I = np.indices(grid.shape(st)).reshape(grid.dim, -1, order="F").T
+        idx.append(I)
+        typ.append(np.full(len(I), q))
+    return np.concatenate(idx), np.concatenate(typ)
+
+
+def colours(grid):
+    """Colour of every sample: 2 q + parity of the anchor index sum."""
+    idx, typ = anchors(grid)
+    return 2 * typ + (idx.sum(axis=1) % 2)
+
+
+def subdomains(grid, active, b, overlap):
+    """Sample-order index arrays of the active samples of every subdomain."""
+    idx, _ = anchors(grid)
+    n_anchor = [q + 1 for q in grid.n]
+    nb = [(m + b - 1) // b for m in n_anchor]
+    out = []
+    for I in np.ndindex(*nb):
+        lo = [max(I[a] * b - overlap, 0) for a in range(grid.dim)]
+        hi = [min(I[a] * b + b + overlap, n_anchor[a]) for a in range(grid.dim)]
+        inside = np.ones(len(idx), dtype=bool)
+        for a in range(grid.dim):
+            inside &= (idx[:, a] >= lo[a]) & (idx[:, a] < hi[a])
+        sel = np.flatnonzero(inside & active)
+        if len(sel):
+            out.append(sel)
+    return out
+
+
+def sgs_sweep(A_loc, r_loc, col_loc):
+    """One symmetric Gauss-Seidel sweep from zero in colour order."""
+    A_loc = sp.csr_matrix(A_loc)
+    d = A_loc.diagonal()
+    x = np.zeros(len(r_loc))
+    order = np.unique(col_loc)
+    for sweep in (order, order[::-1]):
+        for c in sweep:
+            S = np.flatnonzero(col_loc == c)
+            x[S] += (r_loc[S] - A_loc[S] @ x) / d[S]
+    return x
+
+
+def preconditioner(asm, b, overlap):
+    """Returns apply(r_full) -> z_full (sample order) for the assembled
+    system (inactive entries of r ignored, z = 0 there)."""
+    grid = asm.grid
+    A = asm.A_full.tocsr()
+    col = colours(grid)
+    subs = subdomains(grid, asm.active, b, overlap)
+    locs = [(s, A[s][:, s], col[s]) for s in subs]
+
+    def apply(r_full):
+        z = np.zeros(grid.n_samples())
+        for s, A_loc, c_loc in locs:
+            z[s] += sgs_sweep(A_loc, r_full[s], c_loc)
+        return z
+    return apply
+
+
+def pcg(asm, apply_m, tol=1e-10, max_iter=100000):
+    """Textbook PCG on the active samples with the preconditioner apply_m,
+    x0 = 0, stopping on the recursively updated relative residual.  Returns
+    (x_full, iterations)."""
+    A = asm.A_full.tocsr()
+    act = asm.active
+    b = asm.b_full * act
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.linalg.norm(b)
+    if nb == 0:
+        return x, 0
+    z = apply_m(r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while it < max_iter and np.linalg.norm(r) > tol * nb:
+        q = (A @ (p * act)) * act
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        z = apply_m(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        it += 1
+    return x, it
