@@ -21,8 +21,13 @@ independently -- and are defined as follows.
     order, then every colour in reverse order, each sample updated by
     x_s += (r_s - (A_I x)_s) / A_ss.  G_I = (D + U)^-1 D (D + L)^-1 in the
     colour ordering, symmetric positive definite.
-  * Preconditioner: z = sum_I R_I^T G_I R_I r (additive Schwarz; with
-    overlap 0 the subdomains are disjoint: block symmetric Gauss-Seidel).
+  * Preconditioner: z = sum_I R_I^T W_I G_I W_I R_I r, W_I = diag(m_s^-1/2)
+    with m_s the number of subdomains that hold sample s (additive Schwarz
+    with a symmetric partition-of-unity scaling of the overlap; with overlap
+    0 the subdomains are disjoint, m = 1: block symmetric Gauss-Seidel).
+    Without the scaling the overlap is corrected twice: on the test problems
+    PCG then needs more iterations than with no overlap at all (e.g. 274
+    against 211 on a 45^2 drop), with it fewer (180).
 """
 from __future__ import annotations
 
@@ -65,16 +70,23 @@ def subdomains(grid, active, b, overlap):
     return out
 
 
-def sgs_sweep(A_loc, r_loc, col_loc):
-    """One symmetric Gauss-Seidel sweep from zero in colour order."""
+def colour_rows(A_loc, col_loc):
+    """The rows of a subdomain matrix grouped by colour, in colour order."""
     A_loc = sp.csr_matrix(A_loc)
-    d = A_loc.diagonal()
+    out = []
+    for c in np.unique(col_loc):
+        S = np.flatnonzero(col_loc == c)
+        out.append((S, A_loc[S]))
+    return out, A_loc.diagonal()
+
+
+def sgs_sweep(rows, d, r_loc):
+    """One symmetric Gauss-Seidel sweep from zero: every colour in order, then
+    in reverse order (rows, d from colour_rows)."""
     x = np.zeros(len(r_loc))
-    order = np.unique(col_loc)
-    for sweep in (order, order[::-1]):
-        for c in sweep:
-            S = np.flatnonzero(col_loc == c)
-            x[S] += (r_loc[S] - A_loc[S] @ x) / d[S]
+    for order in (rows, rows[::-1]):
+        for S, A_S in order:
+            x[S] += (r_loc[S] - A_S @ x) / d[S]
     return x
 
 
@@ -85,12 +97,18 @@ def preconditioner(asm, b, overlap):
     A = asm.A_full.tocsr()
     col = colours(grid)
     subs = subdomains(grid, asm.active, b, overlap)
-    locs = [(s, A[s][:, s], col[s]) for s in subs]
+    count = np.zeros(grid.n_samples())
+    for s in subs:
+        count[s] += 1
+    locs = []
+    for s in subs:
+        rows, d = colour_rows(A[s][:, s], col[s])
+        locs.append((s, rows, d, 1.0 / np.sqrt(count[s])))
 
     def apply(r_full):
         z = np.zeros(grid.n_samples())
-        for s, A_loc, c_loc in locs:
-            z[s] += sgs_sweep(A_loc, r_full[s], c_loc)
+        for s, rows, d, w in locs:
+            z[s] += w * sgs_sweep(rows, d, w * r_full[s])
         return z
     return apply
 
