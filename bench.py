@@ -412,6 +412,33 @@ def learned_leg(V, ctx, case, u0, plain_solve_ms, plain_iters, max_iter):
                     if conv else f"learned FCG did not reach 1e-6 within {max_iter} iterations"}
 
 
+def plain_preconditioners_leg(V, cases_list):
+    """The plain preconditioners on the same FP64 steps, to 1e-6: Jacobi,
+    block symmetric Gauss-Seidel on bricks (VFS_PRECOND_IC) and overlapping
+    additive Schwarz on bricks (VFS_PRECOND_SCHWARZ), iterations and solve
+    time per configuration (live timing of the Schwarz application)."""
+    out = {}
+    for label, case in cases_list:
+        ctx = V.context_from_case(case, precision=V.VFS_FP64, tol=1e-6)
+        res = {}
+        for name, pc in (("jacobi", V.VFS_PRECOND_JACOBI), ("block_sgs", V.VFS_PRECOND_IC),
+                         ("schwarz", V.VFS_PRECOND_SCHWARZ)):
+            ctx.vfs_set_solver(pc, V.VFS_FP64, 1e-6, 200000)
+            ctx.vfs_set_velocity(case["u"])
+            ctx.vfs_set_profiling(True)
+            ctx.vfs_step(case["dt"])
+            st = ctx.vfs_get_stats()
+            ctx.vfs_set_profiling(False)
+            res[name] = {"iterations": st["iterations"], "solve_ms": st["t_solve_ms"],
+                         "ms_per_iteration": st["t_solve_ms"] / max(1, st["iterations"]),
+                         "rel_residual_fp64": st["rel_residual"],
+                         "precond_avg_ms": st["t_precond_avg_ms"] if pc != V.VFS_PRECOND_JACOBI else None,
+                         "n_active": st["n_active"]}
+        ctx.close()
+        out[label] = res
+    return out
+
+
 def hbm_copy_probe(mib=1024, reps=3):
     """A plain device copy of known size for scaling rocprofv3 FETCH_SIZE /
     WRITE_SIZE readings into bytes: y = x + 0 over mib MiB of float32 reads
@@ -446,6 +473,8 @@ def main():
                     help="skip the 128^3 FP64-vs-mixed leg")
     ap.add_argument("--no-batch64", action="store_true",
                     help="skip the batched 64-problem 2D leg")
+    ap.add_argument("--no-plain-precond", action="store_true",
+                    help="skip the FP64 Jacobi / block-SGS / Schwarz comparison")
     ap.add_argument("--hbm-copy-probe", action="store_true",
                     help="only run the 1 GiB device copy used to scale HBM counters")
     ap.add_argument("--only", choices=["pool512"], default=None,
@@ -547,6 +576,10 @@ def main():
     if not args.no_batch64:
         print("[bench] batched 2D leg", file=sys.stderr, flush=True)
         out["batch64_2d"], batch_got = batch64_leg(V)
+    if not args.no_plain_precond:
+        print("[bench] plain preconditioners leg", file=sys.stderr, flush=True)
+        out["plain_preconditioners_fp64"] = plain_preconditioners_leg(
+            V, [("pool256", cases.pool256()), ("pool512_2d", cases.pool512())])
     base_case = None
     if not args.no_cpu:
         lo = crop_maps.crop_lo(case, (0.5, 0.3, 0.5), args.cpu_crop)

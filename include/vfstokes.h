@@ -58,10 +58,16 @@ extern "C" {
 /* preconditioners */
 #define VFS_PRECOND_NONE     0
 #define VFS_PRECOND_JACOBI   1   /* diagonal of A */
-#define VFS_PRECOND_IC       2   /* reserved for an incomplete-Cholesky factor: no such
-                                    factor is built, vfs_set_solver returns VFS_EINVAL */
+#define VFS_PRECOND_IC       2   /* block symmetric Gauss-Seidel (the IC-style
+                                    factorization (D+L) D^-1 (D+U) of A restricted to
+                                    disjoint bricks of 16^2 / 4^3 anchors, multicolour
+                                    order), VFS_FP64 only */
 #define VFS_PRECOND_LEARNED  3   /* U-Net correction inside flexible CG (3D, VFS_MIXED;
                                     attach a network with vfs_set_preconditioner) */
+#define VFS_PRECOND_SCHWARZ  4   /* overlapping additive Schwarz: the same brick solver on
+                                    bricks extended by one anchor, corrections summed (a
+                                    GPU analogue of the overlapping Schwarz decomposition
+                                    the paper pairs with CG, Sections 7 and 9), VFS_FP64 only */
 
 /* arithmetic of the solve */
 #define VFS_FP64   0   /* FP64 vectors, coefficients, apply and reductions */
@@ -423,7 +429,9 @@ int vfs_load_preconditioner(vfs_ctx* ctx, const void* weights, size_t bytes);
  * e is the exact correction of the residual r. */
 int vfs_training_pair(vfs_ctx* ctx, const double* x_star, const double* x_k, double* r,
                       double* e);
-/* z = network correction of r on the assembled context (sample order). */
+/* z = M^-1 r of the configured preconditioner on the assembled context
+ * (sample order): the brick preconditioners (VFS_PRECOND_IC, _SCHWARZ) in
+ * FP64, otherwise the attached network's two-level correction. */
 int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z);
 
 #ifdef __cplusplus

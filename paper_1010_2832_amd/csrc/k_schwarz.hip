@@ -1,0 +1,440 @@
+// Brick-local Schwarz preconditioners and the FP64 PCG that uses them.
+//
+// Preconditioner (the GPU analogue of the overlapping Schwarz domain
+// decomposition the paper pairs with CG, Section 7's closing paragraph and
+// Section 9): the anchor lattice (every sample of every type anchored at its
+// array index, 0..n per axis) is cut into bricks of B anchors per axis; a
+// brick's subdomain is the active samples anchored in the brick extended by OV
+// anchors on each side.  Each subdomain is solved approximately by one
+// symmetric multicolour Gauss-Seidel sweep on its principal submatrix of A,
+// from zero: colours (sample type q, parity of the anchor index sum) in the
+// order q = 0, 1, ..., parity 0 before 1, forward, then in reverse.  Samples
+// of one colour share no face, so A couples none of them and a colour is
+// relaxed at once.  z = sum over subdomains I of W_I G_I W_I r, W_I =
+// diag(m^-1/2), m the number of extended bricks holding the sample's anchor
+// (a symmetric partition of unity on the overlap): with OV = 0 the bricks are
+// disjoint (m = 1, block symmetric Gauss-Seidel); with OV > 0 the launches
+// take the bricks in 2^d colour classes whose extended bricks do not overlap,
+// so each class adds its corrections without write conflicts.
+//
+// One workgroup per brick keeps the extended brick in LDS: r, a = W_L active,
+// c = W_F W_L / mu (stresses), D^-1 and the local iterate x at its anchors, and
+// the face coefficients K one anchor beyond.  (A_loc x)_s is evaluated
+// matrix-free from the same stencils as the apply kernels:
+//   (A x)_s = a_s sum_f sigma_fs K_f g_f + c_s x_s [+ (1/2) min(c_xx, c_yy) x
+//   of the other diagonal stress in 3D],  g_f = sum_t sigma_ft a_t x_t,
+// with x = 0 outside the subdomain.
+#include <algorithm>
+
+#include "vfs_internal.h"
+#include "vfs_reduce.h"
+
+namespace vfs {
+namespace {
+
+constexpr int NT = 256;
+
+// Face stencils: per face axis, the samples (type, offset of the sample
+// anchor from the face anchor, sign) of (B0 x) at the face.  The terms of a
+// sample's own row are these, transposed.
+struct Term {
+    int8_t q, dx, dy, dz, s;
+};
+
+// 2D: types p, txx, txy; faces u, v
+__constant__ Term kFace2[2][6] = {
+    {{0, 0, 0, 0, 1}, {0, -1, 0, 0, -1}, {1, -1, 0, 0, 1}, {1, 0, 0, 0, -1}, {2, 0, 0, 0, 1}, {2, 0, 1, 0, -1}},
+    {{0, 0, 0, 0, 1}, {0, 0, -1, 0, -1}, {1, 0, 0, 0, 1}, {1, 0, -1, 0, -1}, {2, 0, 0, 0, 1}, {2, 1, 0, 0, -1}},
+};
+// per sample type: (face axis, offset of the face anchor from the sample anchor, sign)
+__constant__ Term kSamp2[3][4] = {
+    {{0, 0, 0, 0, 1}, {0, 1, 0, 0, -1}, {1, 0, 0, 0, 1}, {1, 0, 1, 0, -1}},
+    {{0, 0, 0, 0, -1}, {0, 1, 0, 0, 1}, {1, 0, 0, 0, 1}, {1, 0, 1, 0, -1}},
+    {{0, 0, 0, 0, 1}, {0, 0, -1, 0, -1}, {1, 0, 0, 0, 1}, {1, -1, 0, 0, -1}},
+};
+// 3D: types p, txx, tyy, txy, txz, tyz; faces u, v, w (w has 10 terms, u and v 8)
+__constant__ Term kFace3[3][10] = {
+    {{0, 0, 0, 0, 1}, {0, -1, 0, 0, -1}, {1, -1, 0, 0, 1}, {1, 0, 0, 0, -1}, {3, 0, 0, 0, 1},
+     {3, 0, 1, 0, -1}, {4, 0, 0, 0, 1}, {4, 0, 0, 1, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 1}, {0, 0, -1, 0, -1}, {2, 0, -1, 0, 1}, {2, 0, 0, 0, -1}, {3, 0, 0, 0, 1},
+     {3, 1, 0, 0, -1}, {5, 0, 0, 0, 1}, {5, 0, 0, 1, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 1}, {0, 0, 0, -1, -1}, {1, 0, 0, 0, 1}, {1, 0, 0, -1, -1}, {2, 0, 0, 0, 1},
+     {2, 0, 0, -1, -1}, {4, 0, 0, 0, 1}, {4, 1, 0, 0, -1}, {5, 0, 0, 0, 1}, {5, 0, 1, 0, -1}},
+};
+__constant__ Term kSamp3[6][6] = {
+    {{0, 0, 0, 0, 1}, {0, 1, 0, 0, -1}, {1, 0, 0, 0, 1}, {1, 0, 1, 0, -1}, {2, 0, 0, 0, 1}, {2, 0, 0, 1, -1}},
+    {{0, 1, 0, 0, 1}, {0, 0, 0, 0, -1}, {2, 0, 0, 0, 1}, {2, 0, 0, 1, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{1, 0, 1, 0, 1}, {1, 0, 0, 0, -1}, {2, 0, 0, 0, 1}, {2, 0, 0, 1, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 1}, {0, 0, -1, 0, -1}, {1, 0, 0, 0, 1}, {1, -1, 0, 0, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{0, 0, 0, 0, 1}, {0, 0, 0, -1, -1}, {2, 0, 0, 0, 1}, {2, -1, 0, 0, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+    {{1, 0, 0, 0, 1}, {1, 0, 0, -1, -1}, {2, 0, 0, 0, 1}, {2, 0, -1, 0, -1}, {0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}},
+};
+
+template <int DIM>
+struct Shape;
+template <>
+struct Shape<2> {
+    static constexpr int NS = 3, NF = 2, FT = 6, ST = 4;
+};
+template <>
+struct Shape<3> {
+    static constexpr int NS = 6, NF = 3, FT = 10, ST = 6;
+};
+
+struct SgsArgs {
+    const double* r;
+    const double* a;
+    const double* c;
+    const double* dinv;
+    const double* K;
+    double* z;
+    int nb[3];        // bricks per axis
+    int cls[3];       // brick class of this launch (parity per axis), -1: every brick
+    int accumulate;   // z += correction (overlapping bricks) or z = correction
+    const int* done;  // skip when set (a converged solve)
+};
+
+template <int DIM, int B, int OV>
+__global__ __launch_bounds__(NT) void k_sgs_bricks(Geo g, SgsArgs s) {
+    static_assert(OV == 0 || OV == 1, "the overlap weights assume an overlap of 0 or 1");
+    static_assert(B >= 2, "same-class extended bricks must not overlap");
+    using S = Shape<DIM>;
+    constexpr int E = B + 2 * OV;                              // extended brick
+    constexpr int NE = DIM == 2 ? E * E : E * E * E;           // its anchors
+    constexpr int EK = E + 2;                                  // with a face ring
+    constexpr int NK = DIM == 2 ? EK * EK : EK * EK * EK;
+    __shared__ double sx[S::NS][NE], sa[S::NS][NE], sr[S::NS][NE], sd[S::NS][NE],
+        sc[S::NS][NE];
+    __shared__ double sk[S::NF][NK];
+    if (s.done && *s.done) return;
+
+    // brick of this workgroup
+    int bi[3] = {0, 0, 0};
+    {
+        long long w = blockIdx.x;
+        for (int a = 0; a < DIM; ++a) {
+            const int cnt = s.cls[a] < 0 ? s.nb[a] : (s.nb[a] - s.cls[a] + 1) / 2;
+            const int j = (int)(w % cnt);
+            w /= cnt;
+            bi[a] = s.cls[a] < 0 ? j : 2 * j + s.cls[a];
+        }
+    }
+    const int nmax[3] = {g.nx, g.ny, g.nz};
+    int lo[3] = {0, 0, 0};
+    for (int a = 0; a < DIM; ++a) lo[a] = bi[a] * B - OV;
+    const long long NP = g.NP;
+    auto gidx = [&](int i, int j, int k) { return DIM == 2 ? g.idx(i, j) : g.idx(i, j, k); };
+
+    // m^-1/2 at an anchor: m is the product over the axes of the number of
+    // extended bricks holding the anchor's index on that axis -- its own
+    // brick and, with overlap, the previous one (first index of a brick) or
+    // the next one (last index) where that brick exists
+    auto weight = [&](int gi, int gj, int gk) {
+        if (OV == 0) return 1.0;
+        const int id[3] = {gi, gj, gk};
+        int m = 1;
+        for (int a = 0; a < DIM; ++a) {
+            const int J = id[a] / B, t = id[a] % B;
+            m *= 1 + ((t == 0 && J >= 1) ? 1 : 0) + ((t == B - 1 && J + 1 < s.nb[a]) ? 1 : 0);
+        }
+        return 1.0 / sqrt((double)m);
+    };
+    // load the extended brick (anchors outside 0..n: absent)
+    for (int l = threadIdx.x; l < NE; l += NT) {
+        const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
+        const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
+        const bool in = gi >= 0 && gi <= nmax[0] && gj >= 0 && gj <= nmax[1] &&
+                        (DIM == 2 || (gk >= 0 && gk <= nmax[2]));
+        const long long o = in ? gidx(gi, gj, gk) : 0;
+        const double w = in ? weight(gi, gj, gk) : 0.0;
+        for (int q = 0; q < S::NS; ++q) {
+            sx[q][l] = 0.0;
+            sa[q][l] = in ? s.a[q * NP + o] : 0.0;
+            sr[q][l] = in ? w * s.r[q * NP + o] : 0.0;
+            sd[q][l] = in ? s.dinv[q * NP + o] : 0.0;
+            sc[q][l] = (in && q > 0) ? s.c[q * NP + o] : 0.0;
+        }
+    }
+    // face coefficients on the extended brick and one anchor beyond (the
+    // padded arrays are zero outside each face set)
+    for (int l = threadIdx.x; l < NK; l += NT) {
+        const int li = l % EK, lj = (l / EK) % EK, lk = DIM == 3 ? l / (EK * EK) : 0;
+        const int gi = lo[0] - 1 + li, gj = lo[1] - 1 + lj, gk = lo[2] - 1 + lk;
+        const bool in = gi >= -1 && gi <= nmax[0] + 1 && gj >= -1 && gj <= nmax[1] + 1 &&
+                        (DIM == 2 || (gk >= -1 && gk <= nmax[2] + 1));
+        const long long o = in ? gidx(gi, gj, gk) : 0;
+        for (int f = 0; f < S::NF; ++f) sk[f][l] = in ? s.K[f * NP + o] : 0.0;
+    }
+    __syncthreads();
+
+    auto lin = [&](int li, int lj, int lk) { return li + E * (lj + E * lk); };
+    auto inside = [&](int li, int lj, int lk) {
+        return li >= 0 && li < E && lj >= 0 && lj < E && (DIM == 2 || (lk >= 0 && lk < E));
+    };
+    // g_f = sum_t sigma a_t x_t at the face of axis f anchored at local (fi, fj, fk)
+    auto face_g = [&](int f, int fi, int fj, int fk) {
+        double acc = 0.0;
+        for (int t = 0; t < S::FT; ++t) {
+            const Term tm = DIM == 2 ? kFace2[f][t] : kFace3[f][t];
+            if (tm.s == 0) continue;
+            const int si = fi + tm.dx, sj = fj + tm.dy, sk2 = fk + tm.dz;
+            if (!inside(si, sj, sk2)) continue;
+            const int l = lin(si, sj, sk2);
+            acc += (double)tm.s * sa[tm.q][l] * sx[tm.q][l];
+        }
+        return acc;
+    };
+    constexpr int NCOL = 2 * S::NS;
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        for (int cc = 0; cc < NCOL; ++cc) {
+            const int col = sweep == 0 ? cc : NCOL - 1 - cc;
+            const int q = col >> 1, par = col & 1;
+            for (int l = threadIdx.x; l < NE; l += NT) {
+                const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
+                if (((lo[0] + li + lo[1] + lj + lo[2] + lk) & 1) != par) continue;
+                if (sa[q][l] == 0.0) continue;   // inactive or absent
+                double y = 0.0;
+                for (int t = 0; t < S::ST; ++t) {
+                    const Term tm = DIM == 2 ? kSamp2[q][t] : kSamp3[q][t];
+                    if (tm.s == 0) continue;
+                    const int fi = li + tm.dx, fj = lj + tm.dy, fk = lk + tm.dz;
+                    const double kf = sk[tm.q][(fi + 1) + EK * ((fj + 1) + EK * (DIM == 3 ? fk + 1 : 0))];
+                    if (kf == 0.0) continue;
+                    y += (double)tm.s * kf * face_g(tm.q, fi, fj, fk);
+                }
+                y *= sa[q][l];
+                if (q > 0) y += sc[q][l] * sx[q][l];
+                if (DIM == 3 && (q == 1 || q == 2)) {
+                    const double cross = 0.5 * fmin(sc[1][l], sc[2][l]);
+                    y += cross * sx[q == 1 ? 2 : 1][l];
+                }
+                sx[q][l] += (sr[q][l] - y) * sd[q][l];
+            }
+            __syncthreads();
+        }
+    }
+
+    // write (or add) the correction of the active samples
+    for (int l = threadIdx.x; l < NE; l += NT) {
+        const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
+        const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
+        const bool in = gi >= 0 && gi <= nmax[0] && gj >= 0 && gj <= nmax[1] &&
+                        (DIM == 2 || (gk >= 0 && gk <= nmax[2]));
+        if (!in) continue;
+        const long long o = gidx(gi, gj, gk);
+        const double w = weight(gi, gj, gk);
+        for (int q = 0; q < S::NS; ++q) {
+            if (s.accumulate) {
+                if (sa[q][l] != 0.0) s.z[q * NP + o] += w * sx[q][l];
+            } else {
+                s.z[q * NP + o] = sx[q][l];
+            }
+        }
+    }
+}
+
+// ---- PCG on the padded FP64 vectors (slot sc of the context's scalars) ----
+__global__ __launch_bounds__(NT) void k_pcg_dot(long long n, const double* __restrict__ u,
+                                                const double* __restrict__ v,
+                                                double* __restrict__ part, const int* done) {
+    if (done && *done) return;
+    double acc = 0.0;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < n; t += (long long)gridDim.x * NT)
+        acc += u[t] * v[t];
+    double vv[1] = {acc};
+    block_partial<1, NT>(vv, part, gridDim.x, blockIdx.x);
+}
+
+__device__ double sum_parts(const double* __restrict__ part, int nb) {
+    __shared__ double sw[NT / 64];
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < nb; t += NT) acc += part[t];
+    acc = wave_sum64(acc);
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    double tot = 0.0;
+    for (int w = 0; w < NT / 64; ++w) tot += sw[w];
+    return tot;
+}
+
+// start: bb = b.b from the partials, iteration 0
+// start (keep_bb = 0: bb = b.b from the partials) or restart from the true
+// residual (keep_bb = 1: rr from the partials, bb kept)
+__global__ __launch_bounds__(NT) void k_pcg_start(const double* part, int nb, Scalars* S,
+                                                  double tol, int max_iter, int keep_bb) {
+    const double v = sum_parts(part, nb);
+    if (threadIdx.x == 0) {
+        if (!keep_bb) S->bb = v;
+        const double bb = S->bb;
+        S->rr = v;
+        S->tol2 = tol * tol;
+        S->iter = 0;
+        S->max_iter = max_iter;
+        S->done = bb > 0.0 ? 0 : 1;
+        S->rz[0] = S->rz[1] = 0.0;
+    }
+}
+
+// r.z of this iteration -> beta
+__global__ __launch_bounds__(NT) void k_pcg_rz(const double* part, int nb, Scalars* S) {
+    if (S->done) return;
+    const double rz = sum_parts(part, nb);
+    if (threadIdx.x == 0) {
+        S->beta = S->iter == 0 ? 0.0 : rz / S->rz[0];
+        S->rz[0] = rz;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_pcg_dir(long long n, const double* __restrict__ z,
+                                                double* __restrict__ p, const Scalars* S) {
+    if (S->done) return;
+    const double beta = S->beta;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < n; t += (long long)gridDim.x * NT)
+        p[t] = z[t] + beta * p[t];
+}
+
+// p.Ap -> alpha (breakdown when p.Ap <= 0 or non-finite)
+__global__ __launch_bounds__(NT) void k_pcg_pq(const double* part, int nb, Scalars* S) {
+    if (S->done) return;
+    const double pq = sum_parts(part, nb);
+    if (threadIdx.x == 0) {
+        S->pq = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+            S->done = 3;
+        } else {
+            S->alpha = S->rz[0] / pq;
+        }
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_pcg_update(long long n, double* __restrict__ x,
+                                                   double* __restrict__ r,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ q, const Scalars* S,
+                                                   double* __restrict__ part) {
+    if (S->done) return;
+    const double alpha = S->alpha;
+    double acc = 0.0;
+    for (long long t = (long long)blockIdx.x * NT + threadIdx.x; t < n;
+         t += (long long)gridDim.x * NT) {
+        x[t] += alpha * p[t];
+        const double rn = r[t] - alpha * q[t];
+        r[t] = rn;
+        acc += rn * rn;
+    }
+    double vv[1] = {acc};
+    block_partial<1, NT>(vv, part, gridDim.x, blockIdx.x);
+}
+
+// r.r -> stop test, next iteration
+__global__ __launch_bounds__(NT) void k_pcg_check(const double* part, int nb, Scalars* S) {
+    if (S->done) return;
+    const double rr = sum_parts(part, nb);
+    if (threadIdx.x == 0) {
+        S->rr = rr;
+        S->iter += 1;
+        if (rr <= S->tol2 * S->bb)
+            S->done = 1;
+        else if (!isfinite(rr))
+            S->done = 3;
+        else if (S->iter >= S->max_iter)
+            S->done = 2;
+    }
+}
+
+template <int DIM, int B, int OV>
+void sgs_launch(const Geo& g, const SgsArgs& base, hipStream_t st) {
+    const int n[3] = {g.nx, g.ny, g.nz};
+    SgsArgs s = base;
+    for (int a = 0; a < 3; ++a) s.nb[a] = a < DIM ? (n[a] + 1 + B - 1) / B : 1;
+    if (OV == 0) {
+        long long nbk = 1;
+        for (int a = 0; a < DIM; ++a) {
+            s.cls[a] = -1;
+            nbk *= s.nb[a];
+        }
+        for (int a = DIM; a < 3; ++a) s.cls[a] = -1;
+        s.accumulate = 0;
+        hipLaunchKernelGGL((k_sgs_bricks<DIM, B, OV>), dim3((unsigned)nbk), dim3(NT), 0, st, g, s);
+        return;
+    }
+    s.accumulate = 1;
+    for (int cls = 0; cls < (1 << DIM); ++cls) {
+        long long nbk = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (a < DIM) {
+                s.cls[a] = (cls >> a) & 1;
+                nbk *= (s.nb[a] - s.cls[a] + 1) / 2;
+            } else {
+                s.cls[a] = -1;
+            }
+        }
+        if (nbk == 0) continue;
+        hipLaunchKernelGGL((k_sgs_bricks<DIM, B, OV>), dim3((unsigned)nbk), dim3(NT), 0, st, g, s);
+    }
+}
+
+}  // namespace
+
+int schwarz_brick(int dim, int overlap) {
+    (void)overlap;
+    return dim == 2 ? 16 : 4;
+}
+
+void launch_schwarz(const Geo& g, int overlap, const double* r, const double* a, const double* c,
+                    const double* dinv, const double* K, double* z, const int* done,
+                    hipStream_t st) {
+    SgsArgs s{};
+    s.r = r;
+    s.a = a;
+    s.c = c;
+    s.dinv = dinv;
+    s.K = K;
+    s.z = z;
+    s.done = done;
+    if (overlap > 0) launch_fill(z, (long long)g.nsamp() * g.NP, 0.0, st);
+    if (g.dim == 2) {
+        if (overlap > 0)
+            sgs_launch<2, 16, 1>(g, s, st);
+        else
+            sgs_launch<2, 16, 0>(g, s, st);
+    } else {
+        if (overlap > 0)
+            sgs_launch<3, 4, 1>(g, s, st);
+        else
+            sgs_launch<3, 4, 0>(g, s, st);
+    }
+}
+
+int pcg_blocks(const Geo& g) { return vec_grid_blocks(g); }
+
+void launch_pcg_dot(const Geo& g, const double* u, const double* v, double* part, const int* done,
+                    hipStream_t st) {
+    const long long n = (long long)g.nsamp() * g.NP;
+    hipLaunchKernelGGL(k_pcg_dot, dim3(pcg_blocks(g)), dim3(NT), 0, st, n, u, v, part, done);
+}
+void launch_pcg_start(const double* part, int nb, Scalars* S, double tol, int max_iter,
+                      bool keep_bb, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(NT), 0, st, part, nb, S, tol, max_iter,
+                       keep_bb ? 1 : 0);
+}
+void launch_pcg_rz(const double* part, int nb, Scalars* S, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_rz, dim3(1), dim3(NT), 0, st, part, nb, S);
+}
+void launch_pcg_dir(const Geo& g, const double* z, double* p, const Scalars* S, hipStream_t st) {
+    const long long n = (long long)g.nsamp() * g.NP;
+    hipLaunchKernelGGL(k_pcg_dir, dim3(pcg_blocks(g)), dim3(NT), 0, st, n, z, p, S);
+}
+void launch_pcg_pq(const double* part, int nb, Scalars* S, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_pq, dim3(1), dim3(NT), 0, st, part, nb, S);
+}
+void launch_pcg_update(const Geo& g, double* x, double* r, const double* p, const double* q,
+                       const Scalars* S, double* part, hipStream_t st) {
+    const long long n = (long long)g.nsamp() * g.NP;
+    hipLaunchKernelGGL(k_pcg_update, dim3(pcg_blocks(g)), dim3(NT), 0, st, n, x, r, p, q, S, part);
+}
+void launch_pcg_check(const double* part, int nb, Scalars* S, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(NT), 0, st, part, nb, S);
+}
+
+}  // namespace vfs

@@ -482,6 +482,100 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
     return status;
 }
 
+// FP64 PCG with the brick-local Schwarz (overlap 1) or block symmetric
+// Gauss-Seidel (overlap 0) preconditioner; every scalar stays on the device
+// (Scalars slot 3), the host polls the stop flag once per chunk.  A stop on
+// the recursive residual is confirmed on the true FP64 residual; otherwise
+// PCG restarts from it.
+int solve_schwarz(vfs_ctx* ctx, const double* b, double* x) {
+    const Geo& g = ctx->g;
+    hipStream_t s = ctx->stream;
+    const long long n = (long long)g.nsamp() * g.NP;
+    const int overlap = ctx->precond == VFS_PRECOND_SCHWARZ ? 1 : 0;
+    if (int rc0 = zero_dirs(ctx, false)) return rc0;
+    const Parts P = parts(ctx);
+    double* part = P.B;
+    const int nb = pcg_blocks(g);
+    Scalars* S = ctx->sc + 3;
+    const int* done = &S->done;
+    double* r = ctx->r;
+    double* z = ctx->z;
+    double* p = ctx->p0;
+    double* q = ctx->q;
+    const RedArgs none{ctx->sc + 2, nullptr, 0, nullptr, 0, 0};
+    HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+    HIPCHK(hipMemcpyAsync(r, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_pcg_dot(g, r, r, part, nullptr, s);
+    launch_pcg_start(part, nb, S, ctx->tol, ctx->max_iter, false, s);
+    HIPCHK(hipGetLastError());
+    int total = 0, outer = 0, status = VFS_OK;
+    double rel = 0.0, bb = 0.0;
+    for (;;) {
+        Scalars sc{};
+        int chunk = 8;
+        for (;;) {
+            for (int k = 0; k < chunk; ++k) {
+                const bool timed = ctx->prof && k == 0;
+                if (timed) HIPCHK(hipEventRecord(ctx->pev[3], s));
+                launch_schwarz(g, overlap, r, ctx->a, ctx->c, ctx->dinv, ctx->K, z, done, s);
+                if (timed) HIPCHK(hipEventRecord(ctx->pev[0], s));
+                launch_pcg_dot(g, r, z, part, done, s);
+                launch_pcg_rz(part, nb, S, s);
+                launch_pcg_dir(g, z, p, S, s);
+                launch_apply<double>(g, ctx->tiles, MODE_APPLY, false, nullptr, nullptr, nullptr, p,
+                                     nullptr, q, ctx->a, ctx->c, ctx->K, nullptr, none, s);
+                launch_pcg_dot(g, p, q, part, done, s);
+                launch_pcg_pq(part, nb, S, s);
+                if (timed) HIPCHK(hipEventRecord(ctx->pev[1], s));
+                launch_pcg_update(g, x, r, p, q, S, part, s);
+                launch_pcg_check(part, nb, S, s);
+                if (timed) HIPCHK(hipEventRecord(ctx->pev[2], s));
+            }
+            HIPCHK(hipGetLastError());
+            int rc = read_scalars(ctx, 3, &sc);
+            if (rc) return rc;
+            if (ctx->prof && !sc.done) {
+                ctx->prof_precond_ms += elapsed(ctx->pev[3], ctx->pev[0]);
+                ctx->prof_apply_ms += elapsed(ctx->pev[0], ctx->pev[1]);
+                ctx->prof_update_ms += elapsed(ctx->pev[1], ctx->pev[2]);
+                ++ctx->prof_apply_n;
+                ++ctx->prof_update_n;
+            }
+            if (sc.done) break;
+            chunk = std::min(chunk * 2, 128);
+        }
+        total += sc.iter;
+        bb = sc.bb;
+        if (!(bb > 0.0)) {
+            rel = 0.0;
+            break;
+        }
+        Scalars so{};
+        int rc = true_residual(ctx, b, x, &so);   // r = b - A x
+        if (rc) return rc;
+        rel = std::sqrt(so.aux0 / bb);
+        if (rel <= ctx->tol) break;
+        if (sc.done == 3 || !std::isfinite(rel)) {
+            status = VFS_EBREAKDOWN;
+            break;
+        }
+        if (sc.done == 2 || total >= ctx->max_iter || ++outer > 20) {
+            status = VFS_ENOTCONV;
+            break;
+        }
+        launch_pcg_dot(g, r, r, part, nullptr, s);
+        launch_pcg_start(part, nb, S, ctx->tol, ctx->max_iter - total, true, s);
+        HIPCHK(hipGetLastError());
+    }
+    ctx->stats.iterations = total;
+    ctx->stats.outer_iterations = outer;
+    ctx->stats.rel_residual = rel;
+    ctx->stats.rel_residual_start = bb > 0.0 ? 1.0 : 0.0;
+    ctx->stats.b_norm = std::sqrt(bb);
+    ctx->stats.status = status;
+    return status;
+}
+
 int solve_internal(vfs_ctx* ctx, const double* b, double* x) {
     if (ctx->g.dim == 3 && ctx->tiles.count == 0) {   // nothing active: x = 0
         HIPCHK(hipMemsetAsync(x, 0, (size_t)ctx->g.nsamp() * ctx->g.NP * sizeof(double),
@@ -493,6 +587,8 @@ int solve_internal(vfs_ctx* ctx, const double* b, double* x) {
         ctx->stats.status = VFS_OK;
         return VFS_OK;
     }
+    if (ctx->precond == VFS_PRECOND_IC || ctx->precond == VFS_PRECOND_SCHWARZ)
+        return solve_schwarz(ctx, b, x);
     if (ctx->precision == VFS_MIXED) return solve_mixed(ctx, b, x);
     return solve_fp64(ctx, b, x);
 }
@@ -990,11 +1086,11 @@ int vfs_set_gravity(vfs_ctx* ctx, const double* g) {
 int vfs_set_solver(vfs_ctx* ctx, int precond, int precision, double rel_tol, int max_iter,
                    double w_min) {
     if (!ctx) return VFS_EINVAL;
-    if (precond == VFS_PRECOND_IC)
-        return fail(ctx, VFS_EINVAL, "VFS_PRECOND_IC is reserved: no incomplete-Cholesky "
-                                     "preconditioner is built in this library");
-    if (precond != VFS_PRECOND_JACOBI && precond != VFS_PRECOND_LEARNED)
+    if (precond != VFS_PRECOND_JACOBI && precond != VFS_PRECOND_LEARNED &&
+        precond != VFS_PRECOND_IC && precond != VFS_PRECOND_SCHWARZ)
         return fail(ctx, VFS_EINVAL, "unsupported preconditioner");
+    if ((precond == VFS_PRECOND_IC || precond == VFS_PRECOND_SCHWARZ) && precision != VFS_FP64)
+        return fail(ctx, VFS_EINVAL, "the brick preconditioners run in VFS_FP64");
     if (precision != VFS_FP64 && precision != VFS_MIXED)
         return fail(ctx, VFS_EINVAL, "precision must be VFS_FP64 or VFS_MIXED");
     if (precond == VFS_PRECOND_LEARNED && (ctx->g.dim != 3 || precision != VFS_MIXED))

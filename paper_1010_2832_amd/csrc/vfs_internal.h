@@ -316,6 +316,24 @@ void launch_advect_u(const Geo& g, double dt, const double* uext, double* uout, 
 void launch_advect_phi(const Geo& g, double dt, const double* uext, const double* phi, double* out,
                        hipStream_t s);
 
+// brick-local Schwarz / block symmetric Gauss-Seidel preconditioner and the
+// FP64 PCG around it (k_schwarz.hip)
+int schwarz_brick(int dim, int overlap);
+void launch_schwarz(const Geo& g, int overlap, const double* r, const double* a, const double* c,
+                    const double* dinv, const double* K, double* z, const int* done,
+                    hipStream_t st);
+int pcg_blocks(const Geo& g);
+void launch_pcg_dot(const Geo& g, const double* u, const double* v, double* part, const int* done,
+                    hipStream_t st);
+void launch_pcg_start(const double* part, int nb, Scalars* S, double tol, int max_iter,
+                      bool keep_bb, hipStream_t st);
+void launch_pcg_rz(const double* part, int nb, Scalars* S, hipStream_t st);
+void launch_pcg_dir(const Geo& g, const double* z, double* p, const Scalars* S, hipStream_t st);
+void launch_pcg_pq(const double* part, int nb, Scalars* S, hipStream_t st);
+void launch_pcg_update(const Geo& g, double* x, double* r, const double* p, const double* q,
+                       const Scalars* S, double* part, hipStream_t st);
+void launch_pcg_check(const double* part, int nb, Scalars* S, hipStream_t st);
+
 // packing and checks (k_util.hip)
 void launch_pack(const Geo& g, const int shp[3], const double* src, double* dst, hipStream_t s);
 void launch_unpack(const Geo& g, const int shp[3], const double* src, double* dst, hipStream_t s);

@@ -607,6 +607,18 @@ int vfs_load_preconditioner(vfs_ctx* ctx, const void* weights, size_t bytes) {
 int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z) {
     if (!ctx) return VFS_EINVAL;
     if (!r || !z) return ctx_fail(ctx, VFS_EINVAL, "NULL vector");
+    if (ctx->precond == VFS_PRECOND_IC || ctx->precond == VFS_PRECOND_SCHWARZ) {
+        if (!ctx->assembled) return ctx_fail(ctx, VFS_ESTATE, "call vfs_assemble first");
+        const Geo& g = ctx->g;
+        const long long n = (long long)g.nsamp() * g.NP;
+        int rc = ctx_put_samples(ctx, r, ctx->q);
+        if (rc) return rc;
+        launch_mask(ctx->r, ctx->q, ctx->a, n, ctx->stream);
+        launch_schwarz(g, ctx->precond == VFS_PRECOND_SCHWARZ ? 1 : 0, ctx->r, ctx->a, ctx->c,
+                       ctx->dinv, ctx->K, ctx->z, nullptr, ctx->stream);
+        if (hipGetLastError() != hipSuccess) return ctx_fail(ctx, VFS_EHIP, "launch failed");
+        return ctx_get_samples(ctx, ctx->z, z);
+    }
     vfs_unet* u = ctx->net;
     if (!u) return ctx_fail(ctx, VFS_ESTATE, "no preconditioner network attached");
     int rc = ctx_ready(u, ctx);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvfstokes.so")
 
 VFS_OK, VFS_EINVAL, VFS_ENOMEM, VFS_EHIP, VFS_ENOTCONV, VFS_EBREAKDOWN, VFS_ESTATE = 0, -1, -2, -3, -4, -5, -6
 VFS_PRECOND_NONE, VFS_PRECOND_JACOBI, VFS_PRECOND_IC, VFS_PRECOND_LEARNED = 0, 1, 2, 3
+VFS_PRECOND_SCHWARZ = 4
 VFS_SAMPLE_P, VFS_SAMPLE_TXX = 0, 1
 VFS_SAMPLE_TXY_2D = 2
 VFS_SAMPLE_TYY, VFS_SAMPLE_TXY, VFS_SAMPLE_TXZ, VFS_SAMPLE_TYZ = 2, 3, 4, 5

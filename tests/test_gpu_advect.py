@@ -84,33 +84,46 @@ def test_fractional_steps_match_oracle(name):
 
 
 def test_warm_start_across_steps():
-    """Mixed solves started from the previous step's solution converge to the
-    same velocities as cold starts, from a starting residual well below |b|.
-    (The iteration counts are reported, not asserted: each FP32 inner solve
-    reduces its residual by a bounded factor, so a tight tolerance needs about
-    as many inner iterations from a warm start as from zero.)"""
+    """Mixed solves started from the previous step's solution (masked to the
+    new active set) start from the residual b - A x_prev that the oracle
+    predicts from its own steps, and converge to the oracle's velocities;
+    cold starts start from |b|.  The iteration counts are reported: on this
+    problem the previous solution is no closer than 0 (its residual is 15-30
+    times |b|, the stresses change a lot from step to step), so warm starts
+    gain nothing here."""
     from paper_1010_2832_amd import vfstokes as V
     case = cases.pool2d(96, 7)
     dt = case["dt"]
+    steps = 4
+    want_start, want_u, asms = [1.0], [], []
+    c, prev, xprev = case, None, None
+    for k in range(steps):
+        c, (asm, x, u) = advect.ns_step(c, dt, prev)
+        if xprev is not None:
+            r = asm.b_full - system.apply(asm, xprev * asm.active)
+            want_start.append(np.linalg.norm(r[asm.active]) / np.linalg.norm(asm.b_full))
+        want_u.append(u)
+        asms.append(asm)
+        prev, xprev = asm, x
     res = {}
     for warm in (False, True):
         ctx = gpu_run(case, precision=V.VFS_MIXED, tol=1e-8, step=False)
         ctx.vfs_set_warm_start(warm)
-        its, vel, start = [], [], []
-        for _ in range(4):
+        its, start = [], []
+        for k in range(steps):
             ctx.vfs_advect(dt)
             ctx.vfs_step(dt)
             st = ctx.vfs_get_stats()
             assert st["rel_residual"] <= 1e-8
             its.append(st["iterations"])
             start.append(st["rel_residual_start"])
-            vel.append(np.concatenate([np.ravel(q) for q in ctx.vfs_get_velocity()]))
-        res[warm] = (its, vel, start)
+            err = velocity_rel_linf(asms[k], flat_faces(asms[k].grid, ctx.vfs_get_velocity()),
+                                    want_u[k])
+            assert err <= 1e-4, (warm, k, err)
+        res[warm] = (its, start)
         ctx.close()
-    _banner(f"iterations cold {res[False][0]}, warm {res[True][0]}; starting residual "
-            f"warm {np.round(res[True][2], 5)}")
-    assert res[True][0][0] == res[False][0][0]
-    assert res[False][2] == [1.0] * 4 and res[True][2][0] == 1.0
-    assert max(res[True][2][1:]) < 0.5
-    for vc, vw in zip(res[False][1], res[True][1]):
-        assert np.abs(vc - vw).max() <= 1e-4 * np.abs(vc).max()
+    _banner(f"iterations cold {res[False][0]}, warm {res[True][0]}; starting residual warm "
+            f"{np.round(res[True][1], 5)}, oracle {np.round(want_start, 5)}")
+    assert res[False][1] == [1.0] * steps
+    for got, want in zip(res[True][1], want_start):
+        assert abs(got - want) <= 1e-4 * want, (got, want)

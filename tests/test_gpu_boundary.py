@@ -1,7 +1,6 @@
 """GPU tests of the C-ABI calls that expose the null-space elimination per
 sample type, the residual/correction pairs of the learned preconditioner's
-training data, the context-owned network, and the reserved
-incomplete-Cholesky value.
+training data, and the context-owned network.
 
 Expected values come from the oracle (active sets, b - A x) or are exact
 identities of FP64 arithmetic (x* - x_k is one subtraction on both sides)."""
@@ -97,12 +96,3 @@ def test_load_preconditioner_matches_attached_network():
         c2.vfs_load_preconditioner(w)
     assert ei.value.code == V.VFS_EINVAL
     c2.close()
-
-
-def test_incomplete_cholesky_value_is_reserved():
-    from paper_1010_2832_amd import vfstokes as V
-    ctx = gpu_run(cases.drop32(), step=False)
-    with pytest.raises(V.VfsError) as ei:
-        ctx.vfs_set_solver(V.VFS_PRECOND_IC, V.VFS_FP64, 1e-6, 1000)
-    assert ei.value.code == V.VFS_EINVAL
-    ctx.close()
