@@ -477,7 +477,8 @@ def main():
                     help="skip the FP64 Jacobi / block-SGS / Schwarz comparison")
     ap.add_argument("--hbm-copy-probe", action="store_true",
                     help="only run the 1 GiB device copy used to scale HBM counters")
-    ap.add_argument("--only", choices=["pool512"], default=None,
+    ap.add_argument("--only", choices=["pool512", "column128", "batch64", "learned", "preconds"],
+                    default=None,
                     help="run only this leg and print its figures (for profiling its kernels)")
     args = ap.parse_args()
 
@@ -502,6 +503,28 @@ def main():
     if args.only == "pool512":
         leg, _, _ = pool512_leg(V, dev, stream, args.pool512_steps, 2)
         print(json.dumps({"pool512_2d": leg}), flush=True)
+        return
+    if args.only == "column128":
+        leg, _ = column128_leg(V)
+        print(json.dumps({"column128_fp64_vs_mixed": leg}), flush=True)
+        return
+    if args.only == "batch64":
+        leg, _ = batch64_leg(V)
+        print(json.dumps({"batch64_2d": leg}), flush=True)
+        return
+    if args.only == "preconds":
+        leg = plain_preconditioners_leg(V, [("pool256", cases.pool256()),
+                                            ("pool512_2d", cases.pool512())])
+        print(json.dumps({"plain_preconditioners_fp64": leg}), flush=True)
+        return
+    if args.only == "learned":
+        case = cases.pool256(seed=args.seed, n=args.n)
+        ctx = V.context_from_case(case, precision=V.VFS_MIXED, tol=1e-6)
+        ctx.vfs_set_stream(stream.cuda_stream)
+        u0 = device_faces(case, dev)
+        leg = learned_leg(V, ctx, case, u0, 0.0, 0, args.learned_max_iter)
+        ctx.close()
+        print(json.dumps({"learned": leg}), flush=True)
         return
     case = cases.pool256(seed=args.seed, n=args.n)
     ctx = V.context_from_case(case, precision=V.VFS_MIXED, tol=1e-6)

@@ -94,18 +94,28 @@ struct SgsArgs {
     const int* done;  // skip when set (a converged solve)
 };
 
+// threads of a brick workgroup: one per anchor of the extended brick
 template <int DIM, int B, int OV>
-__global__ __launch_bounds__(NT) void k_sgs_bricks(Geo g, SgsArgs s) {
+struct BrickShape {
+    static constexpr int E = B + 2 * OV;                        // extended brick
+    static constexpr int NE = DIM == 2 ? E * E : E * E * E;     // its anchors
+    static constexpr int EK = E + 2;                            // with a face ring
+    static constexpr int NK = DIM == 2 ? EK * EK : EK * EK * EK;
+    static constexpr int T = (NE + 63) / 64 * 64;
+};
+
+template <int DIM, int B, int OV>
+__global__ __launch_bounds__((BrickShape<DIM, B, OV>::T)) void k_sgs_bricks(Geo g, SgsArgs s) {
     static_assert(OV == 0 || OV == 1, "the overlap weights assume an overlap of 0 or 1");
     static_assert(B >= 2, "same-class extended bricks must not overlap");
     using S = Shape<DIM>;
-    constexpr int E = B + 2 * OV;                              // extended brick
-    constexpr int NE = DIM == 2 ? E * E : E * E * E;           // its anchors
-    constexpr int EK = E + 2;                                  // with a face ring
-    constexpr int NK = DIM == 2 ? EK * EK : EK * EK * EK;
+    using BS = BrickShape<DIM, B, OV>;
+    constexpr int E = BS::E, NE = BS::NE, EK = BS::EK, NK = BS::NK, T = BS::T;
+    // per anchor: local iterate, a, (weighted) r, D^-1, c; per face: K and the
+    // face value g = sum_t sigma a_t x_t of the current local iterate
     __shared__ double sx[S::NS][NE], sa[S::NS][NE], sr[S::NS][NE], sd[S::NS][NE],
         sc[S::NS][NE];
-    __shared__ double sk[S::NF][NK];
+    __shared__ double sk[S::NF][NK], sg[S::NF][NK];
     if (s.done && *s.done) return;
 
     // brick of this workgroup
@@ -124,7 +134,6 @@ __global__ __launch_bounds__(NT) void k_sgs_bricks(Geo g, SgsArgs s) {
     for (int a = 0; a < DIM; ++a) lo[a] = bi[a] * B - OV;
     const long long NP = g.NP;
     auto gidx = [&](int i, int j, int k) { return DIM == 2 ? g.idx(i, j) : g.idx(i, j, k); };
-
     // m^-1/2 at an anchor: m is the product over the axes of the number of
     // extended bricks holding the anchor's index on that axis -- its own
     // brick and, with overlap, the previous one (first index of a brick) or
@@ -139,14 +148,17 @@ __global__ __launch_bounds__(NT) void k_sgs_bricks(Geo g, SgsArgs s) {
         }
         return 1.0 / sqrt((double)m);
     };
-    // load the extended brick (anchors outside 0..n: absent)
-    for (int l = threadIdx.x; l < NE; l += NT) {
-        const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
-        const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
-        const bool in = gi >= 0 && gi <= nmax[0] && gj >= 0 && gj <= nmax[1] &&
-                        (DIM == 2 || (gk >= 0 && gk <= nmax[2]));
-        const long long o = in ? gidx(gi, gj, gk) : 0;
-        const double w = in ? weight(gi, gj, gk) : 0.0;
+
+    // this thread's anchor (anchors outside 0..n are absent)
+    const int l = threadIdx.x;
+    const bool mine = l < NE;
+    const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
+    const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
+    const bool in = mine && gi >= 0 && gi <= nmax[0] && gj >= 0 && gj <= nmax[1] &&
+                    (DIM == 2 || (gk >= 0 && gk <= nmax[2]));
+    const long long o = in ? gidx(gi, gj, gk) : 0;
+    const double w = in ? weight(gi, gj, gk) : 0.0;
+    if (mine) {
         for (int q = 0; q < S::NS; ++q) {
             sx[q][l] = 0.0;
             sa[q][l] = in ? s.a[q * NP + o] : 0.0;
@@ -157,72 +169,60 @@ __global__ __launch_bounds__(NT) void k_sgs_bricks(Geo g, SgsArgs s) {
     }
     // face coefficients on the extended brick and one anchor beyond (the
     // padded arrays are zero outside each face set)
-    for (int l = threadIdx.x; l < NK; l += NT) {
-        const int li = l % EK, lj = (l / EK) % EK, lk = DIM == 3 ? l / (EK * EK) : 0;
-        const int gi = lo[0] - 1 + li, gj = lo[1] - 1 + lj, gk = lo[2] - 1 + lk;
-        const bool in = gi >= -1 && gi <= nmax[0] + 1 && gj >= -1 && gj <= nmax[1] + 1 &&
-                        (DIM == 2 || (gk >= -1 && gk <= nmax[2] + 1));
-        const long long o = in ? gidx(gi, gj, gk) : 0;
-        for (int f = 0; f < S::NF; ++f) sk[f][l] = in ? s.K[f * NP + o] : 0.0;
+    for (int e = threadIdx.x; e < NK; e += T) {
+        const int ei = e % EK, ej = (e / EK) % EK, ek = DIM == 3 ? e / (EK * EK) : 0;
+        const int fi = lo[0] - 1 + ei, fj = lo[1] - 1 + ej, fk = lo[2] - 1 + ek;
+        const bool fin = fi >= -1 && fi <= nmax[0] + 1 && fj >= -1 && fj <= nmax[1] + 1 &&
+                         (DIM == 2 || (fk >= -1 && fk <= nmax[2] + 1));
+        const long long fo = fin ? gidx(fi, fj, fk) : 0;
+        for (int f = 0; f < S::NF; ++f) {
+            sk[f][e] = fin ? s.K[f * NP + fo] : 0.0;
+            sg[f][e] = 0.0;
+        }
     }
     __syncthreads();
 
-    auto lin = [&](int li, int lj, int lk) { return li + E * (lj + E * lk); };
-    auto inside = [&](int li, int lj, int lk) {
-        return li >= 0 && li < E && lj >= 0 && lj < E && (DIM == 2 || (lk >= 0 && lk < E));
+    // local index of the face anchored at this anchor + (dx, dy, dz)
+    auto fidx = [&](const Term& tm) {
+        return (li + tm.dx + 1) + EK * ((lj + tm.dy + 1) + EK * (DIM == 3 ? lk + tm.dz + 1 : 0));
     };
-    // g_f = sum_t sigma a_t x_t at the face of axis f anchored at local (fi, fj, fk)
-    auto face_g = [&](int f, int fi, int fj, int fk) {
-        double acc = 0.0;
-        for (int t = 0; t < S::FT; ++t) {
-            const Term tm = DIM == 2 ? kFace2[f][t] : kFace3[f][t];
-            if (tm.s == 0) continue;
-            const int si = fi + tm.dx, sj = fj + tm.dy, sk2 = fk + tm.dz;
-            if (!inside(si, sj, sk2)) continue;
-            const int l = lin(si, sj, sk2);
-            acc += (double)tm.s * sa[tm.q][l] * sx[tm.q][l];
-        }
-        return acc;
-    };
+    const int par_l = (lo[0] + li + lo[1] + lj + lo[2] + lk) & 1;
     constexpr int NCOL = 2 * S::NS;
     for (int sweep = 0; sweep < 2; ++sweep) {
         for (int cc = 0; cc < NCOL; ++cc) {
             const int col = sweep == 0 ? cc : NCOL - 1 - cc;
             const int q = col >> 1, par = col & 1;
-            for (int l = threadIdx.x; l < NE; l += NT) {
-                const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
-                if (((lo[0] + li + lo[1] + lj + lo[2] + lk) & 1) != par) continue;
-                if (sa[q][l] == 0.0) continue;   // inactive or absent
+            // samples of one colour share no face: their updates of the face
+            // values below never meet
+            if (mine && par_l == par && sa[q][l] != 0.0) {
                 double y = 0.0;
                 for (int t = 0; t < S::ST; ++t) {
                     const Term tm = DIM == 2 ? kSamp2[q][t] : kSamp3[q][t];
                     if (tm.s == 0) continue;
-                    const int fi = li + tm.dx, fj = lj + tm.dy, fk = lk + tm.dz;
-                    const double kf = sk[tm.q][(fi + 1) + EK * ((fj + 1) + EK * (DIM == 3 ? fk + 1 : 0))];
-                    if (kf == 0.0) continue;
-                    y += (double)tm.s * kf * face_g(tm.q, fi, fj, fk);
+                    const int fe = fidx(tm);
+                    y += (double)tm.s * sk[tm.q][fe] * sg[tm.q][fe];
                 }
-                y *= sa[q][l];
+                const double aq = sa[q][l];
+                y *= aq;
                 if (q > 0) y += sc[q][l] * sx[q][l];
                 if (DIM == 3 && (q == 1 || q == 2)) {
                     const double cross = 0.5 * fmin(sc[1][l], sc[2][l]);
                     y += cross * sx[q == 1 ? 2 : 1][l];
                 }
-                sx[q][l] += (sr[q][l] - y) * sd[q][l];
+                const double dx = (sr[q][l] - y) * sd[q][l];
+                sx[q][l] += dx;
+                for (int t = 0; t < S::ST; ++t) {
+                    const Term tm = DIM == 2 ? kSamp2[q][t] : kSamp3[q][t];
+                    if (tm.s == 0) continue;
+                    sg[tm.q][fidx(tm)] += (double)tm.s * aq * dx;
+                }
             }
             __syncthreads();
         }
     }
 
     // write (or add) the correction of the active samples
-    for (int l = threadIdx.x; l < NE; l += NT) {
-        const int li = l % E, lj = (l / E) % E, lk = DIM == 3 ? l / (E * E) : 0;
-        const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
-        const bool in = gi >= 0 && gi <= nmax[0] && gj >= 0 && gj <= nmax[1] &&
-                        (DIM == 2 || (gk >= 0 && gk <= nmax[2]));
-        if (!in) continue;
-        const long long o = gidx(gi, gj, gk);
-        const double w = weight(gi, gj, gk);
+    if (in) {
         for (int q = 0; q < S::NS; ++q) {
             if (s.accumulate) {
                 if (sa[q][l] != 0.0) s.z[q * NP + o] += w * sx[q][l];
@@ -355,7 +355,8 @@ void sgs_launch(const Geo& g, const SgsArgs& base, hipStream_t st) {
         }
         for (int a = DIM; a < 3; ++a) s.cls[a] = -1;
         s.accumulate = 0;
-        hipLaunchKernelGGL((k_sgs_bricks<DIM, B, OV>), dim3((unsigned)nbk), dim3(NT), 0, st, g, s);
+        hipLaunchKernelGGL((k_sgs_bricks<DIM, B, OV>), dim3((unsigned)nbk),
+                           dim3(BrickShape<DIM, B, OV>::T), 0, st, g, s);
         return;
     }
     s.accumulate = 1;
@@ -370,7 +371,8 @@ void sgs_launch(const Geo& g, const SgsArgs& base, hipStream_t st) {
             }
         }
         if (nbk == 0) continue;
-        hipLaunchKernelGGL((k_sgs_bricks<DIM, B, OV>), dim3((unsigned)nbk), dim3(NT), 0, st, g, s);
+        hipLaunchKernelGGL((k_sgs_bricks<DIM, B, OV>), dim3((unsigned)nbk),
+                           dim3(BrickShape<DIM, B, OV>::T), 0, st, g, s);
     }
 }
 
