@@ -233,7 +233,7 @@ def cpu_oracle_leg(baseline_case, iters, main_out, batch_out, baseline=True, che
     return res
 
 
-WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_96_long.npy")
+WEIGHTS = os.path.join(ROOT, "paper_1010_2832_amd", "weights", "pool3d_64_128.npy")
 
 
 def column128_leg(V):
@@ -384,12 +384,13 @@ def pool512_leg(V, dev, stream, steps, warmup):
     return out, got, case
 
 
-def learned_leg(V, ctx, case, u0, plain_solve_ms, plain_iters, max_iter):
+def learned_leg(V, ctx, case, u0, plain_solve_ms, plain_iters, max_iter, weights=None):
     """Flexible CG with the committed network on the headline step, to 1e-6
     or `max_iter` iterations, beside the plain Jacobi-PCG solve of the same
     step.  Non-convergence is reported as such, with the residual reached."""
     import numpy as np
-    w = np.load(WEIGHTS, allow_pickle=False).astype(np.float32)
+    weights = weights or WEIGHTS
+    w = np.load(weights, allow_pickle=False).astype(np.float32)
     ctx.vfs_load_preconditioner(w)
     ctx.vfs_set_solver(V.VFS_PRECOND_LEARNED, V.VFS_MIXED, 1e-6, max_iter)
     ctx.vfs_set_velocity(u0)
@@ -400,7 +401,7 @@ def learned_leg(V, ctx, case, u0, plain_solve_ms, plain_iters, max_iter):
     ctx.vfs_set_preconditioner(None)
     ctx.vfs_set_solver(V.VFS_PRECOND_JACOBI, V.VFS_MIXED, 1e-6, 200000)
     conv = sl["rel_residual"] <= 1e-6
-    return {"weights": os.path.relpath(WEIGHTS, ROOT), "iteration_cap": max_iter,
+    return {"weights": os.path.relpath(weights, ROOT), "iteration_cap": max_iter,
             "converged": bool(conv), "iterations": sl["iterations"],
             "solve_ms": sl["t_solve_ms"], "rel_residual_fp64": sl["rel_residual"],
             "ms_per_iteration": sl["t_solve_ms"] / max(1, sl["iterations"]),
@@ -466,6 +467,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=400)
     ap.add_argument("--cpu-crop", type=int, default=64)
     ap.add_argument("--learned-max-iter", type=int, default=6000)
+    ap.add_argument("--weights", default=None, help="network weights (.npy) of the learned leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-FCG leg")
     ap.add_argument("--no-pool512", action="store_true", help="skip the 2D 512^2 leg")
     ap.add_argument("--pool512-steps", type=int, default=10)
@@ -522,7 +524,7 @@ def main():
         ctx = V.context_from_case(case, precision=V.VFS_MIXED, tol=1e-6)
         ctx.vfs_set_stream(stream.cuda_stream)
         u0 = device_faces(case, dev)
-        leg = learned_leg(V, ctx, case, u0, 0.0, 0, args.learned_max_iter)
+        leg = learned_leg(V, ctx, case, u0, 0.0, 0, args.learned_max_iter, args.weights)
         ctx.close()
         print(json.dumps({"learned": leg}), flush=True)
         return
@@ -584,7 +586,8 @@ def main():
         print("[bench] learned FCG leg", file=sys.stderr, flush=True)
         plain_ms = sorted(solve_ms)[len(solve_ms) // 2]
         out["learned_vs_plain"] = learned_leg(V, ctx, case, u0, plain_ms,
-                                              per[-1]["iterations"], args.learned_max_iter)
+                                              per[-1]["iterations"], args.learned_max_iter,
+                                              args.weights)
     ctx.close()
     extra3d = [("headline", case, crop_maps.sites_pool, {"plain_jacobi_pcg": head_got})]
     extra2d, batch_got = [], None
