@@ -525,21 +525,71 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
 // two buffers by launch parity because the halo of launch k reads the values
 // of launch k-1 that neighbouring workgroups overwrite.  The raw inputs of
 // plane k+2 are loaded while plane k is computed, as in k_dir3d_pipe.
+//
+// Work tiles are 64 x FTY anchors marching FKZ planes (FTY / 4 x FKZ / 8 list
+// tiles), so the halo ring costs 2 rows per FTY and 2 planes per FKZ.  Every
+// solver vector is zero on a sample with a = 0 (inactive samples have
+// a = c = D^-1 = 0, the solve starts from zero there and nothing is ever
+// stored there), so a 64-wide row of one sample slice whose row bit is clear
+// is neither loaded nor stored: its values are known to be 0.
+//
+// When nx is a multiple of 64 the anchors i = 0..nx need one x tile more than
+// nx / 64, and that tile holds only the column i = nx, where only tau_xy and
+// tau_xz exist (on the wall x = nx h).  The fused work tiles then stop one x
+// tile earlier and the last of them also owns that column: the threads that
+// load its x halo at i = nx (rows j0 .. j0 + FTY - 1) carry out the update of
+// those two samples and form their outputs from the face values already in
+// LDS (the v and w faces at i = nx do not exist and count as 0).
+#ifndef VFS_FUSED3_FOLD
+#define VFS_FUSED3_FOLD 1
+#endif
+constexpr int FTY = kFused3Y, FKZ = kFused3Z, FNT = 64 * FTY;
+constexpr int FHY = FTY + 2, FFY = FTY + 1;
+
+// the last x tile is folded into the one before it (nx a multiple of 64)
+__host__ __device__ __forceinline__ bool fused_fold(int nx) {
+    return VFS_FUSED3_FOLD && nx >= TX && nx % TX == 0;
+}
+
+// row bits of x tile t, row (j, k); 0 outside the anchors of the grid
+__device__ __forceinline__ unsigned row_bits_at(const Geo& g, const uint8_t* __restrict__ rows,
+                                                int ntx, int t, int j, int k) {
+    if (t < 0 || t >= ntx || j < 0 || j > g.ny || k < 0 || k > g.nz) return 0u;
+    return rows[t + (long long)ntx * (j + (long long)(g.ny + 1) * k)];
+}
+
+// Anchors of fused work item u: x from i0, y from j0, planes [k0, kend).
+__device__ __forceinline__ void fused_origin(const Tiles& t, const Geo& g, int u, int& tx, int& j0,
+                                             int& k0, int& kend) {
+    const int id = t.list[u / t.split];
+    tx = id % t.ntx;
+    const int ty = (id / t.ntx) % t.nty;
+    const int tz = id / (t.ntx * t.nty);
+    const int kz = FKZ / t.split;
+    j0 = ty * FTY;
+    k0 = tz * FKZ + (u % t.split) * kz;
+    kend = min(k0 + kz, g.nz + 1);
+}
+
 template <typename T>
 struct FusedOwn {
     T r[6], q[6], p[6], d[6], a[6], x[6];
+    unsigned m;   // row bits of the plane
 };
 template <typename T>
 struct FusedHalo {
     T r[6], q[6], p[6], d[6], a[6];
+    T x3, x4, c3, c4;   // x and c of tau_xy, tau_xz in the folded column i = nx
+    unsigned m;
 };
 
 template <typename T, bool INIT>
-__global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
-                                                const T* __restrict__ dinv,
-                                                const T* __restrict__ a,
-                                                const T* __restrict__ c,
-                                                const T* __restrict__ K, RedArgs ra) {
+__global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
+                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ a,
+                                                 const T* __restrict__ c,
+                                                 const T* __restrict__ K,
+                                                 const uint8_t* __restrict__ rows, RedArgs ra) {
     Scalars* sc = ra.sc;
     const int kidx = ra.kidx;
     const int pin = (kidx + 1) & 1, pout = kidx & 1;   // launch k reads (k-1)&1, writes k&1
@@ -552,7 +602,7 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
     T* __restrict__ x = static_cast<T*>(v.x);
 
     // totals of the previous launch -> stop decision, alpha_{k-1}, beta_k
-    PartialLoads<5, NT, 4> pl;
+    PartialLoads<5, FNT, 2> pl;
     if (!INIT) pl.load(ra.part_in, ra.nb_in);
     if (!INIT && sc->done) return;
     T alpha = T(0), beta = T(0);
@@ -590,70 +640,89 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
         beta = (T)bd;
     }
 
-    __shared__ T sW[2][6][HY][HX];
-    __shared__ T gU[2][FY][FX];
-    __shared__ T gV[2][FY][FX];
-    __shared__ T gW[2][FY][FX];
+    __shared__ T sW[2][6][FHY][HX];
+    __shared__ T gU[2][FFY][FX];
+    __shared__ T gV[2][FFY][FX];
+    __shared__ T gW[2][FFY][FX];
+    __shared__ T sXF[2][FTY][2][5];     // folded column: p, a, z, D^-1, c per plane parity
+    __shared__ unsigned sXM[2][FTY];    // and its row bits
     const long long NP = g.NP;
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
-    const bool hrole = tid < 2 * HX + 2 * TY;
+    const bool hrole = tid < 2 * HX + 2 * FTY;
     int hli = 0, hlj = 0;
     if (tid < HX) {
         hli = tid;
         hlj = 0;
     } else if (tid < 2 * HX) {
         hli = tid - HX;
-        hlj = HY - 1;
+        hlj = FHY - 1;
     } else if (hrole) {
         const int e = tid - 2 * HX;
         hlj = 1 + (e >> 1);
         hli = (e & 1) ? HX - 1 : 0;
     }
-    constexpr int NF = (FX * FY + NT - 1) / NT;
+    // x tile of the halo position relative to the work tile's (-1, 0, +1)
+    const int hdt = hli == 0 ? -1 : (hli == HX - 1 ? 1 : 0);
+    const int rntx = (g.nx + TX) / TX;   // x tiles of the row bits
+    const bool fold = fused_fold(g.nx);
+    // right x-halo threads of the own rows: owners of the folded column
+    const bool xrole = fold && hrole && tid >= 2 * HX && hli == HX - 1;
+    constexpr int NF = (FX * FFY + FNT - 1) / FNT;
     double rz_n = 0.0, rr_n = 0.0, pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
-    const TileRange trg = tile_range(tl.items());
+    const TileRange trg = tile_range(ft.items());
     for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
-        int i0, j0, k0, kend;
-        tile_origin(tl, g, wtile, i0, j0, k0, kend);
+        int xt, j0, k0, kend;
+        fused_origin(ft, g, wtile, xt, j0, k0, kend);
+        const int i0 = xt * TX;
         const int io = i0 + tx, jo = j0 + ty;
         const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
+        // this thread also owns anchor (nx, jh) of the folded column
+        const bool xown = xrole && xt == ft.ntx - 1 && jh <= g.ny;
 
         auto fetch = [&](int kk, FusedOwn<T>& o, FusedHalo<T>& h) {
-            const bool ino = io <= g.nx + 1 && jo <= g.ny + 1 && kk <= g.nz + 1;
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
-            const long long oo = ino ? g.idx(io, jo, kk) : 0;
-            const bool inh = hrole && ih <= g.nx + 1 && jh <= g.ny + 1 && kk <= g.nz + 1;
-            const long long oh = inh ? g.idx(ih, jh, kk) : 0;
+            o.m = io <= g.nx + 1 ? row_bits_at(g, rows, rntx, xt, jo, kk) : 0u;
+            const long long oo = o.m ? g.idx(io, jo, kk) : 0;
+            h.m = (hrole && ih <= g.nx + 1) ? row_bits_at(g, rows, rntx, xt + hdt, jh, kk) : 0u;
+            const long long oh = h.m ? g.idx(ih, jh, kk) : 0;
+            const bool hx = xown && kk >= k0 && kk < kend;
+            const bool h3 = hx && ((h.m >> 3) & 1u), h4 = hx && ((h.m >> 4) & 1u);
+            h.x3 = (h3 && !INIT) ? x[3 * NP + oh] : T(0);
+            h.x4 = (h4 && !INIT) ? x[4 * NP + oh] : T(0);
+            h.c3 = h3 ? c[3 * NP + oh] : T(0);
+            h.c4 = h4 ? c[4 * NP + oh] : T(0);
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
                 const long long so = oo + s * NP, sh = oh + s * NP;
-                o.r[s] = ino ? r_in[so] : T(0);
-                o.d[s] = ino ? dinv[so] : T(0);
-                o.a[s] = ino ? a[so] : T(0);
-                o.q[s] = (ino && !INIT) ? q_in[so] : T(0);
-                o.p[s] = (ino && !INIT) ? p_in[so] : T(0);
-                o.x[s] = (own && !INIT) ? x[so] : T(0);
-                h.r[s] = inh ? r_in[sh] : T(0);
-                h.d[s] = inh ? dinv[sh] : T(0);
-                h.a[s] = inh ? a[sh] : T(0);
-                h.q[s] = (inh && !INIT) ? q_in[sh] : T(0);
-                h.p[s] = (inh && !INIT) ? p_in[sh] : T(0);
+                const bool lo = (o.m >> s) & 1u, lh = (h.m >> s) & 1u;
+                o.r[s] = lo ? r_in[so] : T(0);
+                o.d[s] = lo ? dinv[so] : T(0);
+                o.a[s] = lo ? a[so] : T(0);
+                o.q[s] = (lo && !INIT) ? q_in[so] : T(0);
+                o.p[s] = (lo && !INIT) ? p_in[so] : T(0);
+                o.x[s] = (lo && own && !INIT) ? x[so] : T(0);
+                h.r[s] = lh ? r_in[sh] : T(0);
+                h.d[s] = lh ? dinv[sh] : T(0);
+                h.a[s] = lh ? a[sh] : T(0);
+                h.q[s] = (lh && !INIT) ? q_in[sh] : T(0);
+                h.p[s] = (lh && !INIT) ? p_in[sh] : T(0);
             }
         };
         // r_k, z_k, p_k of plane kk into the ring slot; own anchors also store
-        // r_k, x_k, p_k and add to r.z, r.r; own p, a, z, D^-1 out
+        // r_k, x_k, p_k and add to r.z, r.r; own p, a, z, D^-1 and row bits out
         auto commit = [&](int kk, const FusedOwn<T>& o, const FusedHalo<T>& h, T (&vo)[6],
-                          T (&ao)[6], T (&zo)[6], T (&dq)[6]) {
+                          T (&ao)[6], T (&zo)[6], T (&dq)[6], unsigned& mo) {
             const int sl = kk & 1;
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
             const long long oo = own ? g.idx(io, jo, kk) : 0;
+            mo = own ? o.m : 0u;
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
                 const T rn = INIT ? o.r[s] : o.r[s] - alpha * o.q[s];
                 const T zn = o.d[s] * rn;
                 const T pn = INIT ? zn : zn + beta * o.p[s];
-                if (own) {
+                if ((mo >> s) & 1u) {
                     const long long os = oo + s * NP;
                     if (!INIT) {
                         r_out[os] = rn;
@@ -678,14 +747,44 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
                     sW[sl][s][hlj][hli] = h.a[s] * pn;
                 }
             }
+            // the folded column: tau_xy (slice 3) and tau_xz (slice 4) at
+            // (nx, jh); what its outputs need later waits in this thread's
+            // LDS slots (registers are exhausted)
+            if (xown) {
+                const unsigned xm = (kk >= k0 && kk < kend) ? (h.m & 0x18u) : 0u;
+                sXM[sl][hlj - 1] = xm;
+                const long long oh = xm ? g.idx(ih, jh, kk) : 0;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int s = 3 + e;
+                    if (!((xm >> s) & 1u)) continue;
+                    const T rn = INIT ? h.r[s] : h.r[s] - alpha * h.q[s];
+                    const T zn = h.d[s] * rn;
+                    const T pn = INIT ? zn : zn + beta * h.p[s];
+                    T* f = sXF[sl][hlj - 1][e];
+                    f[0] = pn;
+                    f[1] = h.a[s];
+                    f[2] = zn;
+                    f[3] = h.d[s];
+                    f[4] = e ? h.c4 : h.c3;
+                    const long long os = oh + s * NP;
+                    if (!INIT) {
+                        r_out[os] = rn;
+                        x[os] = (e ? h.x4 : h.x3) + alpha * h.p[s];
+                    }
+                    p_out[os] = pn;
+                    rz_n += (double)rn * (double)zn;
+                    rr_n += (double)rn * (double)rn;
+                }
+            }
         };
         auto fetchK = [&](int kk, T (&ku)[NF], T (&kv)[NF], T (&kw)[NF]) {
 #pragma unroll
             for (int m = 0; m < NF; ++m) {
-                const int e = tid + m * NT;
+                const int e = tid + m * FNT;
                 const int li = e % FX, lj = e / FX;
                 ku[m] = kv[m] = kw[m] = T(0);
-                if (e < FX * FY) {
+                if (e < FX * FFY) {
                     const int iu = i0 + li, ju = j0 - 1 + lj;
                     if (iu <= g.nx && ju >= 0 && ju < g.ny && kk >= 0 && kk < g.nz)
                         ku[m] = K[g.idx(iu, ju, kk)];
@@ -702,8 +801,8 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
             const int s0 = kk & 1, s1 = (kk + 1) & 1;
 #pragma unroll
             for (int m = 0; m < NF; ++m) {
-                const int e = tid + m * NT;
-                if (e >= FX * FY) continue;
+                const int e = tid + m * FNT;
+                if (e >= FX * FFY) continue;
                 const int li = e % FX, lj = e / FX;
                 gU[s0][lj][li] = ku[m] * ((sW[s0][0][lj][li + 1] - sW[s0][0][lj][li]) +
                                           (sW[s0][1][lj][li] - sW[s0][1][lj][li + 1]) +
@@ -720,40 +819,41 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
                                           (sW[s1][5][lj][li] - sW[s1][5][lj + 1][li]));
             }
         };
-        auto fetchC = [&](int kk, T (&cc)[5]) {
-            const bool ok = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
-            const long long o = ok ? g.idx(io, jo, kk) : 0;
+        // compliance coefficients of the own anchor of plane kk (row bits m)
+        auto fetchC = [&](int kk, unsigned m, T (&cc)[5]) {
+            const long long o = m ? g.idx(io, jo, kk) : 0;
 #pragma unroll
-            for (int s = 0; s < 5; ++s) cc[s] = ok ? c[(s + 1) * NP + o] : T(0);
+            for (int s = 0; s < 5; ++s) cc[s] = ((m >> (s + 1)) & 1u) ? c[(s + 1) * NP + o] : T(0);
         };
 
         T vcur[6], acur[6], zcur[6], dcur[6], vnext[6], anext[6], znext[6], dnext[6];
+        unsigned mcur, mnext;
         FusedOwn<T> Fo;
         FusedHalo<T> Fh;
         T Ku[NF], Kv[NF], Kw[NF], Cc[5];
         __syncthreads();   // LDS of the previous tile is no longer read
         fetch(k0 - 1, Fo, Fh);
         fetchK(k0 - 1, Ku, Kv, Kw);
-        commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext);
+        commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext, mnext);
         fetch(k0, Fo, Fh);
-        commit(k0, Fo, Fh, vcur, acur, zcur, dcur);
+        commit(k0, Fo, Fh, vcur, acur, zcur, dcur, mcur);
         fetch(k0 + 1, Fo, Fh);
         __syncthreads();
         faces(k0 - 1, Ku, Kv, Kw);
         fetchK(k0, Ku, Kv, Kw);
-        fetchC(k0, Cc);
+        fetchC(k0, mcur, Cc);
         __syncthreads();
 
         for (int k = k0; k < kend; ++k) {
-            commit(k + 1, Fo, Fh, vnext, anext, znext, dnext);
+            commit(k + 1, Fo, Fh, vnext, anext, znext, dnext, mnext);
             if (k + 2 <= kend) fetch(k + 2, Fo, Fh);
             __syncthreads();
             faces(k, Ku, Kv, Kw);
             T Cn[5];
             fetchK(k + 1, Ku, Kv, Kw);
-            fetchC(k + 1, Cn);
+            fetchC(k + 1, mnext, Cn);
             __syncthreads();
-            if (io <= g.nx && jo <= g.ny) {
+            if (mcur) {
                 const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;
                 const T gu0 = gU[sk][ty + 1][tx], gu1 = gU[sk][ty + 1][tx + 1];
                 const T gum = gU[sk][ty][tx], guz = gU[sp][ty + 1][tx];
@@ -773,11 +873,32 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
                 y[5] = acur[5] * ((gv0 - gvz) + (gw0 - gwy)) + Cc[4] * vcur[5];
 #pragma unroll
                 for (int s = 0; s < 6; ++s) {
+                    if (!((mcur >> s) & 1u)) continue;
                     q_out[s * NP + o] = y[s];
                     const double yd = y[s];
                     pq_n += (double)vcur[s] * yd;
                     qz_n += (double)zcur[s] * yd;
                     qdq_n += (double)dcur[s] * yd * yd;
+                }
+            }
+            const unsigned xmc = xown ? sXM[k & 1][hlj - 1] : 0u;
+            if (xmc) {   // anchor (nx, jh): faces u at li = 64, v and w at li = 63
+                const int sk = k & 1, sp = (k - 1) & 1;
+                const T gu0 = gU[sk][hlj][TX], gum = gU[sk][hlj - 1][TX];
+                const T guz = gU[sp][hlj][TX];
+                const T gvm = gV[sk][hlj - 1][TX], gwx = gW[sk][hlj][TX];
+                const T fl[2] = {(gu0 - gum) - gvm, (gu0 - guz) - gwx};
+                const long long o = g.idx(ih, jh, k);
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    if (!((xmc >> (3 + e)) & 1u)) continue;
+                    const T* f = sXF[sk][hlj - 1][e];
+                    const T y = f[1] * fl[e] + f[4] * f[0];
+                    q_out[(3 + e) * NP + o] = y;
+                    const double yd = y;
+                    pq_n += (double)f[0] * yd;
+                    qz_n += (double)f[2] * yd;
+                    qdq_n += (double)f[3] * yd * yd;
                 }
             }
 #pragma unroll
@@ -787,12 +908,13 @@ __global__ __launch_bounds__(NT) void k_fused3d(Geo g, Tiles tl, FusedVecs v,
                 zcur[s] = znext[s];
                 dcur[s] = dnext[s];
             }
+            mcur = mnext;
 #pragma unroll
             for (int s = 0; s < 5; ++s) Cc[s] = Cn[s];
         }
     }
     double vv[5] = {rz_n, pq_n, qz_n, qdq_n, rr_n};
-    block_partial<5, NT>(vv, ra.part_out, gridDim.x, blockIdx.x);
+    block_partial<5, FNT>(vv, ra.part_out, gridDim.x, blockIdx.x);
 }
 
 // x += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r over the active tiles
@@ -891,6 +1013,47 @@ __global__ __launch_bounds__(1024) void k_tile_compact(int n, const int* __restr
         if (flags[t]) list[w++] = t;
 }
 
+// a fused work tile (tx, fy, fz) is active if one of its list tiles is (with
+// the folded last x tile for the last fused x tile)
+__global__ void k_fused_flags(int ntx, int nty, int ntz, int fnx, int fny, int fnz,
+                              const int* __restrict__ tflags, int* __restrict__ fflags) {
+    constexpr int SY = FTY / TY, SZ = FKZ / KZ;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= fnx * fny * fnz) return;
+    const int fx = id % fnx, fy = (id / fnx) % fny, fz = id / (fnx * fny);
+    const int tx1 = fx == fnx - 1 ? ntx - 1 : fx;
+    int any = 0;
+    for (int tx = fx; tx <= tx1; ++tx)
+        for (int dz = 0; dz < SZ; ++dz)
+            for (int dy = 0; dy < SY; ++dy) {
+                const int ty = fy * SY + dy, tz = fz * SZ + dz;
+                if (ty < nty && tz < ntz) any |= tflags[tx + ntx * (ty + nty * tz)];
+            }
+    fflags[id] = any ? 1 : 0;
+}
+
+// One wave per row (x tile t, y, z): bit s of the row's byte is set if an
+// anchor i = 64 t .. 64 t + 63 (i <= nx) has a != 0 in sample slice s.
+__global__ __launch_bounds__(256) void k_row_bits(Geo g, int ntx, const double* __restrict__ a,
+                                                  uint8_t* __restrict__ rows, long long nrows) {
+    const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= nrows) return;   // whole waves
+    const int lane = threadIdx.x & 63;
+    const int t = (int)(row % ntx);
+    const long long jk = row / ntx;
+    const int j = (int)(jk % (g.ny + 1)), k = (int)(jk / (g.ny + 1));
+    const int i = t * TX + lane;
+    int bits = 0;
+    if (i <= g.nx) {
+        const long long o = g.idx(i, j, k);
+        for (int s = 0; s < 6; ++s)
+            if (a[s * g.NP + o] != 0.0) bits |= 1 << s;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+    if (lane == 0) rows[row] = (uint8_t)bits;
+}
+
 }  // namespace
 
 void tile_dims(const Geo& g, int& ntx, int& nty, int& ntz) {
@@ -906,6 +1069,37 @@ void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* cou
     const int n = ntx * nty * ntz;
     hipLaunchKernelGGL(k_tile_flags, dim3(n), dim3(NT), 0, s, g, ntx, nty, ntz, a, flags);
     hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, n, flags, list, count);
+}
+
+void fused_tile_dims(const Geo& g, int& ntx, int& nty, int& ntz) {
+    ntx = (g.nx + 1 + TX - 1) / TX - (fused_fold(g.nx) ? 1 : 0);
+    nty = (g.ny + 1 + FTY - 1) / FTY;
+    ntz = (g.nz + 1 + FKZ - 1) / FKZ;
+}
+
+void launch_fused_tiles(const Geo& g, const int* tile_flags, int* flags, int* list, int* count,
+                        hipStream_t s) {
+    int ntx, nty, ntz, fx, fy, fz;
+    tile_dims(g, ntx, nty, ntz);
+    fused_tile_dims(g, fx, fy, fz);
+    const int n = fx * fy * fz;
+    hipLaunchKernelGGL(k_fused_flags, dim3((n + 255) / 256), dim3(256), 0, s, ntx, nty, ntz, fx,
+                       fy, fz, tile_flags, flags);
+    hipLaunchKernelGGL(k_tile_compact, dim3(1), dim3(1024), 0, s, n, flags, list, count);
+}
+
+long long row_bytes(const Geo& g) {
+    int ntx, nty, ntz;
+    tile_dims(g, ntx, nty, ntz);
+    return (long long)ntx * (g.ny + 1) * (g.nz + 1);
+}
+
+void launch_row_bits(const Geo& g, const double* a, uint8_t* rows, hipStream_t s) {
+    int ntx, nty, ntz;
+    tile_dims(g, ntx, nty, ntz);
+    const long long n = row_bytes(g);
+    hipLaunchKernelGGL(k_row_bits, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, g, ntx, a, rows,
+                       n);
 }
 
 // Workgroups of a 3D apply launch: no more than can be resident at once
@@ -954,6 +1148,13 @@ int tile_split(int count, int capacity) {
     return split;
 }
 
+// the same for the fused work tiles (at most FKZ / 4 parts of 4 planes)
+int fused_split(int count, int capacity) {
+    int split = 1;
+    while (split < FKZ / 4 && (long long)count * split * 2 <= capacity) split *= 2;
+    return split;
+}
+
 // The update is elementwise, with no halo and no plane-to-plane dependence:
 // a short tile list gives it one plane per work item (split KZ), as long as
 // that does not exceed the grid cap, whatever split the applies use.
@@ -975,7 +1176,7 @@ int fused3d_grid(int count) {
     int& c = cache[dev & 15];
     if (c == 0) {
         int nb = 0, ncu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused3d<float, false>, NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused3d<float, false>, FNT, 0) !=
                 hipSuccess ||
             nb < 1)
             nb = 1;
@@ -987,17 +1188,17 @@ int fused3d_grid(int count) {
     return std::max(1, std::min(std::min(count, kMaxTileBlocks), c));
 }
 
-void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v,
+void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v,
                     const float* dinv, const float* a, const float* c, const float* K,
-                    const RedArgs& ra, hipStream_t s) {
-    if (tl.count <= 0) return;
-    const dim3 gs(fused3d_grid(tl.items()));
+                    const uint8_t* rows, const RedArgs& ra, hipStream_t s) {
+    if (ft.count <= 0) return;
+    const dim3 gs(fused3d_grid(ft.items()));
     if (init)
-        hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(NT), 0, s, g, tl, v, dinv, a, c, K,
-                           ra);
+        hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(FNT), 0, s, g, ft, v, dinv, a, c, K,
+                           rows, ra);
     else
-        hipLaunchKernelGGL((k_fused3d<float, false>), gs, dim3(NT), 0, s, g, tl, v, dinv, a, c, K,
-                           ra);
+        hipLaunchKernelGGL((k_fused3d<float, false>), gs, dim3(FNT), 0, s, g, ft, v, dinv, a, c, K,
+                           rows, ra);
 }
 
 template <typename T>

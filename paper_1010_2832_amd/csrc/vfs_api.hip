@@ -226,11 +226,12 @@ int run_chunks_fused(vfs_ctx* ctx, bool set_bb, Scalars* out) {
 int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     const Geo& g = ctx->g;
     hipStream_t s = ctx->stream;
-    const int nb = fused3d_grid(ctx->tiles.items());
+    const int nb = fused3d_grid(ctx->ftiles.items());
     double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)kMaxTileBlocks + 32};
     const FusedVecs fv{ctx->x32, {ctx->r32, ctx->z32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
     const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
-    launch_fused3d(g, ctx->tiles, true, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32, r0, s);
+    launch_fused3d(g, ctx->ftiles, true, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32,
+                   ctx->rowbits, r0, s);
     int chunk = 8;
     int kidx = 1;
     for (;;) {
@@ -238,8 +239,8 @@ int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
             const RedArgs ra{ctx->sc, part[(kidx + 1) & 1], nb, part[kidx & 1], kidx,
                              (set_bb && kidx == 1) ? 1 : 0};
             if (ctx->prof && k == 1) HIPCHK(hipEventRecord(ctx->pev[0], s));
-            launch_fused3d(g, ctx->tiles, false, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32, ra,
-                           s);
+            launch_fused3d(g, ctx->ftiles, false, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32,
+                           ctx->rowbits, ra, s);
         }
         if (ctx->prof) HIPCHK(hipEventRecord(ctx->pev[1], s));
         HIPCHK(hipGetLastError());
@@ -644,16 +645,22 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
     }
     if (g.dim == 3) {
         launch_tiles(g, ctx->a, ctx->tile_flags, ctx->tile_list, ctx->tile_count, s);
-        HIPCHK(hipMemcpyAsync(ctx->tile_count_host, ctx->tile_count, sizeof(int),
+        launch_fused_tiles(g, ctx->tile_flags, ctx->ftile_flags, ctx->ftile_list,
+                           ctx->tile_count + 1, s);
+        launch_row_bits(g, ctx->a, ctx->rowbits, s);
+        HIPCHK(hipMemcpyAsync(ctx->tile_count_host, ctx->tile_count, 2 * sizeof(int),
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         ctx->tiles.list = ctx->tile_list;
-        ctx->tiles.count = *ctx->tile_count_host;
-        // main kernel of the solve: the fused FP32 iteration (mixed) or the
-        // pipelined FP64 direction + apply
+        ctx->tiles.count = ctx->tile_count_host[0];
+        ctx->ftiles.list = ctx->ftile_list;
+        ctx->ftiles.count = ctx->tile_count_host[1];
+        // main kernel of the solve: the fused FP32 iteration (mixed, over its
+        // own work tiles) or the pipelined FP64 direction + apply
         const int cap = ctx->precision == VFS_MIXED ? fused3d_grid(1 << 30)
                                                     : dir3d_grid(1 << 30, (int)sizeof(double));
         ctx->tiles.split = tile_split(ctx->tiles.count, cap);
+        ctx->ftiles.split = fused_split(ctx->ftiles.count, fused3d_grid(1 << 30));
         ctx->stats.n_tile_samples = (int64_t)ctx->tiles.count * tile3d_anchors() * g.nsamp();
     }
     if (ctx->precision == VFS_MIXED) {
@@ -794,6 +801,9 @@ int vfs_destroy(vfs_ctx* ctx) {
     if (ctx->tile_flags) (void)hipFree(ctx->tile_flags);
     if (ctx->tile_list) (void)hipFree(ctx->tile_list);
     if (ctx->tile_count) (void)hipFree(ctx->tile_count);
+    if (ctx->ftile_flags) (void)hipFree(ctx->ftile_flags);
+    if (ctx->ftile_list) (void)hipFree(ctx->ftile_list);
+    if (ctx->rowbits) (void)hipFree(ctx->rowbits);
     if (ctx->tile_count_host) (void)hipHostFree(ctx->tile_count_host);
     if (ctx->sc_host) (void)hipHostFree(ctx->sc_host);
     if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
@@ -883,6 +893,11 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
         ALLOC(ctx->tile_flags, nt);
         ALLOC(ctx->tile_list, nt);
         ALLOC(ctx->tile_count, 4);
+        fused_tile_dims(g, ctx->ftiles.ntx, ctx->ftiles.nty, ctx->ftiles.ntz);
+        const long long nf = (long long)ctx->ftiles.ntx * ctx->ftiles.nty * ctx->ftiles.ntz;
+        ALLOC(ctx->ftile_flags, nf);
+        ALLOC(ctx->ftile_list, nf);
+        ALLOC(ctx->rowbits, row_bytes(g));
     } else {
         ALLOC(ctx->tile_flags, nt2);
         ALLOC(ctx->tile_list, nt2);

@@ -31,6 +31,18 @@ constexpr int kFront = 16;
 constexpr int kMaxTileBlocks = 1536;
 // 3D tile: 64 x 4 anchors in x, y, marching 8 planes in z
 constexpr int kTile3X = 64, kTile3Y = 4, kTile3Z = 8;
+// Work tile of the fused 3D CG iteration: 64 x kFused3Y anchors marching
+// kFused3Z planes, a whole number of the tiles above in y and z (fewer halo
+// rows and planes per anchor than one tile).
+#ifndef VFS_FUSED3_Y
+#define VFS_FUSED3_Y 4
+#endif
+#ifndef VFS_FUSED3_Z
+#define VFS_FUSED3_Z 8
+#endif
+constexpr int kFused3Y = VFS_FUSED3_Y, kFused3Z = VFS_FUSED3_Z;
+static_assert(kFused3Y % kTile3Y == 0 && kFused3Z % kTile3Z == 0 && kFused3Y <= 16,
+              "a fused tile holds whole tiles and at most 1024 threads");
 
 struct Geo {
     int dim;
@@ -239,6 +251,13 @@ struct vfs_ctx {
     int* tile_count_host = nullptr;  // pinned
     vfs::Tiles tiles{nullptr, 0, 0, 0, 0};
     int tiles2d = 0;                 // 2D: active tiles of the fused CG (in tile_list)
+    // 3D: work tiles of the fused iteration holding an active tile, and one
+    // byte per 64-anchor row (x tile, y, z) with bit s set if sample slice s
+    // has an active sample in the row
+    int* ftile_flags = nullptr;
+    int* ftile_list = nullptr;
+    vfs::Tiles ftiles{nullptr, 0, 0, 0, 0};
+    uint8_t* rowbits = nullptr;
 
     bool assembled = false;
     double dt_assembled = 0.0;
@@ -363,10 +382,19 @@ int dir_apply_blocks(const Geo& g, const Tiles& tl, int word);
 int apply3d_grid(int count, int word);
 int dir3d_grid(int count, int word);
 // one launch per Jacobi-PCG iteration in 3D (FP32), k_apply3d.hip
+// over the work tiles of fused_tile_dims (the list launch_fused_tiles builds
+// from the tile flags), skipping the rows of rowbits without an active sample
 int fused3d_grid(int count);
-void launch_fused3d(const Geo& g, const Tiles& tl, bool init, const FusedVecs& v,
+void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v,
                     const float* dinv, const float* a, const float* c, const float* K,
-                    const RedArgs& ra, hipStream_t s);
+                    const uint8_t* rows, const RedArgs& ra, hipStream_t s);
+void fused_tile_dims(const Geo& g, int& ntx, int& nty, int& ntz);
+void launch_fused_tiles(const Geo& g, const int* tile_flags, int* flags, int* list, int* count,
+                        hipStream_t s);
+// plane split of the fused work tiles (their Tiles::split)
+int fused_split(int count, int capacity);
+long long row_bytes(const Geo& g);
+void launch_row_bits(const Geo& g, const double* a, uint8_t* rows, hipStream_t s);
 // anchor positions of one tile of the 3D kernels and of the fused 2D kernel
 int tile3d_anchors();
 // plane split of a 3D tile list (Tiles::split)

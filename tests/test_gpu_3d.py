@@ -35,6 +35,11 @@ CASES = {
     "rand8": lambda: _random3d(8, 8, 8, 1),
     "rand13x7x9": lambda: _random3d(13, 7, 9, 2),
     "rand70x9x11": lambda: _random3d(70, 9, 11, 3),
+    # nx a multiple of 64: the anchors i = 0..nx take one 64-wide x tile more,
+    # holding only the wall column i = nx, which the fused mixed iteration
+    # folds into the x tile before it
+    "rand64x9x11": lambda: _random3d(64, 9, 11, 6),
+    "rand128x6x5": lambda: _random3d(128, 6, 5, 7),
     "column32": lambda: cases.column3d(32, seed=3),
     "pool24": lambda: cases.pool3d(24, seed=5),
 }
@@ -93,7 +98,8 @@ def test_step_fp64_3d(name):
     assert system.true_relative_residual(asm, ctx.vfs_get_solution()) <= 1e-10
 
 
-@pytest.mark.parametrize("name", ["rand13x7x9", "column32", "pool24"])
+@pytest.mark.parametrize("name", ["rand13x7x9", "rand70x9x11", "rand64x9x11", "rand128x6x5",
+                                  "column32", "pool24"])
 def test_step_mixed_3d(name):
     _banner(f"step mixed {name}")
     case = CASES[name]()
