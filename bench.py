@@ -280,7 +280,7 @@ BATCH_TOL = 1e-9
 def batch64_leg(V):
     """Many uneven 2D solves in one persistent, graph-captured launch: the 64
     problems of sizes {64, 96, ..., 512}^2, tile shape and workgroups per CU
-    picked by the autotuner, mixed precision to 1e-6.  Reports the solve time,
+    picked by the autotuner, mixed precision to BATCH_TOL.  Reports the solve time,
     aggregate DOF*iter/s and per-problem latency percentiles; returns with
     them host copies of the velocity and solution of the smallest, middle and
     largest problems for the CPU leg to check."""

@@ -123,10 +123,11 @@ typedef struct vfs_stats {
     double  t_update_avg_ms;
     int64_t n_apply_timed;
     int64_t n_update_timed;
-    /* learned preconditioner (VFS_PRECOND_LEARNED): average device time of
-       one network application (scale, pack, forward, unpack) under
-       profiling, and the number of iterations whose network direction was
-       not a descent direction and was replaced by the Jacobi one */
+    /* preconditioned solves (VFS_PRECOND_LEARNED, _IC, _SCHWARZ): average
+       device time of one preconditioner application under profiling (for
+       the network: scale, pack, forward, unpack); for the learned solve also
+       the number of iterations whose network direction was not a descent
+       direction and was replaced by the Jacobi one */
     double  t_precond_avg_ms;
     int32_t precond_fallbacks;
     int32_t pad0;
@@ -136,8 +137,9 @@ typedef struct vfs_stats {
        Set by assembly.  In 2D it describes the VFS_MIXED (fused) solve; the
        2D VFS_FP64 kernels sweep the whole grid. */
     int64_t n_tile_samples;
-    /* ||b - A x0|| / ||b|| of the last solve's starting iterate x0 (1 from
-       zero; below 1 when warm-started, vfs_set_warm_start) */
+    /* ||b - A x0|| / ||b|| of the last solve's starting iterate x0: 1 from
+       zero; when warm-started (vfs_set_warm_start) that of the previous
+       solution masked to the new active set, which may well exceed 1 */
     double  rel_residual_start;
 } vfs_stats;
 

@@ -526,15 +526,16 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
 // of launch k-1 that neighbouring workgroups overwrite.  The raw inputs of
 // plane k+2 are loaded while plane k is computed, as in k_dir3d_pipe.
 //
-// Work tiles are 64 x FTY anchors marching FKZ planes (FTY / 4 x FKZ / 8 list
-// tiles), so the halo ring costs 2 rows per FTY and 2 planes per FKZ.  Every
-// solver vector is zero on a sample with a = 0 (inactive samples have
-// a = c = D^-1 = 0, the solve starts from zero there and nothing is ever
-// stored there), so a 64-wide row of one sample slice whose row bit is clear
-// is neither loaded nor stored: its values are known to be 0.
+// Work tiles are FTX x FTY anchors marching FKZ planes (a part of one list
+// tile in x, FTY / 4 x FKZ / 8 list tiles in y and z), so the halo ring costs
+// 2 rows per FTY, 2 columns per FTX and 2 planes per FKZ.  Every solver vector
+// is zero on a sample with a = 0 (inactive samples have a = c = D^-1 = 0, the
+// solve starts from zero there and nothing is ever stored there), so an
+// FTX-wide row of one sample slice whose row bit is clear is neither loaded
+// nor stored: its values are known to be 0.
 //
-// When nx is a multiple of 64 the anchors i = 0..nx need one x tile more than
-// nx / 64, and that tile holds only the column i = nx, where only tau_xy and
+// When nx is a multiple of FTX the anchors i = 0..nx need one x tile more than
+// nx / FTX, and that tile holds only the column i = nx, where only tau_xy and
 // tau_xz exist (on the wall x = nx h).  The fused work tiles then stop one x
 // tile earlier and the last of them also owns that column: the threads that
 // load its x halo at i = nx (rows j0 .. j0 + FTY - 1) carry out the update of
@@ -543,12 +544,12 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
 #ifndef VFS_FUSED3_FOLD
 #define VFS_FUSED3_FOLD 1
 #endif
-constexpr int FTY = kFused3Y, FKZ = kFused3Z, FNT = 64 * FTY;
-constexpr int FHY = FTY + 2, FFY = FTY + 1;
+constexpr int FTX = kFused3X, FTY = kFused3Y, FKZ = kFused3Z, FNT = FTX * FTY;
+constexpr int FHX = FTX + 2, FHY = FTY + 2, FFX = FTX + 1, FFY = FTY + 1;
 
-// the last x tile is folded into the one before it (nx a multiple of 64)
+// the last x tile is folded into the one before it (nx a multiple of FTX)
 __host__ __device__ __forceinline__ bool fused_fold(int nx) {
-    return VFS_FUSED3_FOLD && nx >= TX && nx % TX == 0;
+    return VFS_FUSED3_FOLD && nx >= FTX && nx % FTX == 0;
 }
 
 // row bits of x tile t, row (j, k); 0 outside the anchors of the grid
@@ -640,41 +641,41 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
         beta = (T)bd;
     }
 
-    __shared__ T sW[2][6][FHY][HX];
-    __shared__ T gU[2][FFY][FX];
-    __shared__ T gV[2][FFY][FX];
-    __shared__ T gW[2][FFY][FX];
+    __shared__ T sW[2][6][FHY][FHX];
+    __shared__ T gU[2][FFY][FFX];
+    __shared__ T gV[2][FFY][FFX];
+    __shared__ T gW[2][FFY][FFX];
     __shared__ T sXF[2][FTY][2][5];     // folded column: p, a, z, D^-1, c per plane parity
     __shared__ unsigned sXM[2][FTY];    // and its row bits
     const long long NP = g.NP;
     const int tid = threadIdx.x;
-    const int tx = tid & 63, ty = tid >> 6;
-    const bool hrole = tid < 2 * HX + 2 * FTY;
+    const int tx = tid % FTX, ty = tid / FTX;
+    const bool hrole = tid < 2 * FHX + 2 * FTY;
     int hli = 0, hlj = 0;
-    if (tid < HX) {
+    if (tid < FHX) {
         hli = tid;
         hlj = 0;
-    } else if (tid < 2 * HX) {
-        hli = tid - HX;
+    } else if (tid < 2 * FHX) {
+        hli = tid - FHX;
         hlj = FHY - 1;
     } else if (hrole) {
-        const int e = tid - 2 * HX;
+        const int e = tid - 2 * FHX;
         hlj = 1 + (e >> 1);
-        hli = (e & 1) ? HX - 1 : 0;
+        hli = (e & 1) ? FHX - 1 : 0;
     }
     // x tile of the halo position relative to the work tile's (-1, 0, +1)
-    const int hdt = hli == 0 ? -1 : (hli == HX - 1 ? 1 : 0);
-    const int rntx = (g.nx + TX) / TX;   // x tiles of the row bits
+    const int hdt = hli == 0 ? -1 : (hli == FHX - 1 ? 1 : 0);
+    const int rntx = (g.nx + kRow3X) / kRow3X;   // x parts of the row bits
     const bool fold = fused_fold(g.nx);
     // right x-halo threads of the own rows: owners of the folded column
-    const bool xrole = fold && hrole && tid >= 2 * HX && hli == HX - 1;
-    constexpr int NF = (FX * FFY + FNT - 1) / FNT;
+    const bool xrole = fold && hrole && tid >= 2 * FHX && hli == FHX - 1;
+    constexpr int NF = (FFX * FFY + FNT - 1) / FNT;
     double rz_n = 0.0, rr_n = 0.0, pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
     const TileRange trg = tile_range(ft.items());
     for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
         int xt, j0, k0, kend;
         fused_origin(ft, g, wtile, xt, j0, k0, kend);
-        const int i0 = xt * TX;
+        const int i0 = xt * FTX;
         const int io = i0 + tx, jo = j0 + ty;
         const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
         // this thread also owns anchor (nx, jh) of the folded column
@@ -782,9 +783,9 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
 #pragma unroll
             for (int m = 0; m < NF; ++m) {
                 const int e = tid + m * FNT;
-                const int li = e % FX, lj = e / FX;
+                const int li = e % FFX, lj = e / FFX;
                 ku[m] = kv[m] = kw[m] = T(0);
-                if (e < FX * FFY) {
+                if (e < FFX * FFY) {
                     const int iu = i0 + li, ju = j0 - 1 + lj;
                     if (iu <= g.nx && ju >= 0 && ju < g.ny && kk >= 0 && kk < g.nz)
                         ku[m] = K[g.idx(iu, ju, kk)];
@@ -802,8 +803,8 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
 #pragma unroll
             for (int m = 0; m < NF; ++m) {
                 const int e = tid + m * FNT;
-                if (e >= FX * FFY) continue;
-                const int li = e % FX, lj = e / FX;
+                if (e >= FFX * FFY) continue;
+                const int li = e % FFX, lj = e / FFX;
                 gU[s0][lj][li] = ku[m] * ((sW[s0][0][lj][li + 1] - sW[s0][0][lj][li]) +
                                           (sW[s0][1][lj][li] - sW[s0][1][lj][li + 1]) +
                                           (sW[s0][3][lj][li + 1] - sW[s0][3][lj + 1][li + 1]) +
@@ -882,11 +883,11 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                 }
             }
             const unsigned xmc = xown ? sXM[k & 1][hlj - 1] : 0u;
-            if (xmc) {   // anchor (nx, jh): faces u at li = 64, v and w at li = 63
+            if (xmc) {   // anchor (nx, jh): faces u at li = FTX, v and w at li = FTX - 1
                 const int sk = k & 1, sp = (k - 1) & 1;
-                const T gu0 = gU[sk][hlj][TX], gum = gU[sk][hlj - 1][TX];
-                const T guz = gU[sp][hlj][TX];
-                const T gvm = gV[sk][hlj - 1][TX], gwx = gW[sk][hlj][TX];
+                const T gu0 = gU[sk][hlj][FTX], gum = gU[sk][hlj - 1][FTX];
+                const T guz = gU[sp][hlj][FTX];
+                const T gvm = gV[sk][hlj - 1][FTX], gwx = gW[sk][hlj][FTX];
                 const T fl[2] = {(gu0 - gum) - gvm, (gu0 - guz) - gwx};
                 const long long o = g.idx(ih, jh, k);
 #pragma unroll
@@ -1013,17 +1014,18 @@ __global__ __launch_bounds__(1024) void k_tile_compact(int n, const int* __restr
         if (flags[t]) list[w++] = t;
 }
 
-// a fused work tile (tx, fy, fz) is active if one of its list tiles is (with
-// the folded last x tile for the last fused x tile)
+// a fused work tile (fx, fy, fz) is active if one of the list tiles it
+// overlaps is (with the folded column i = nx for the last fused x tile)
 __global__ void k_fused_flags(int ntx, int nty, int ntz, int fnx, int fny, int fnz,
                               const int* __restrict__ tflags, int* __restrict__ fflags) {
     constexpr int SY = FTY / TY, SZ = FKZ / KZ;
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
     if (id >= fnx * fny * fnz) return;
     const int fx = id % fnx, fy = (id / fnx) % fny, fz = id / (fnx * fny);
-    const int tx1 = fx == fnx - 1 ? ntx - 1 : fx;
+    const int tx0 = fx * FTX / TX;
+    const int tx1 = fx == fnx - 1 ? ntx - 1 : (fx * FTX + FTX - 1) / TX;
     int any = 0;
-    for (int tx = fx; tx <= tx1; ++tx)
+    for (int tx = tx0; tx <= tx1; ++tx)
         for (int dz = 0; dz < SZ; ++dz)
             for (int dy = 0; dy < SY; ++dy) {
                 const int ty = fy * SY + dy, tz = fz * SZ + dz;
@@ -1032,26 +1034,28 @@ __global__ void k_fused_flags(int ntx, int nty, int ntz, int fnx, int fny, int f
     fflags[id] = any ? 1 : 0;
 }
 
-// One wave per row (x tile t, y, z): bit s of the row's byte is set if an
-// anchor i = 64 t .. 64 t + 63 (i <= nx) has a != 0 in sample slice s.
+// kRow3X lanes per row (x part t, y, z): bit s of the row's byte is set if
+// an anchor i = RW t .. RW t + RW - 1 (i <= nx) has a != 0 in sample slice s.
 __global__ __launch_bounds__(256) void k_row_bits(Geo g, int ntx, const double* __restrict__ a,
                                                   uint8_t* __restrict__ rows, long long nrows) {
-    const long long row = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= nrows) return;   // whole waves
-    const int lane = threadIdx.x & 63;
-    const int t = (int)(row % ntx);
-    const long long jk = row / ntx;
-    const int j = (int)(jk % (g.ny + 1)), k = (int)(jk / (g.ny + 1));
-    const int i = t * TX + lane;
+    constexpr int RW = kRow3X;
+    const long long row = ((long long)blockIdx.x * 256 + threadIdx.x) / RW;
+    const int lane = threadIdx.x % RW;
     int bits = 0;
-    if (i <= g.nx) {
-        const long long o = g.idx(i, j, k);
-        for (int s = 0; s < 6; ++s)
-            if (a[s * g.NP + o] != 0.0) bits |= 1 << s;
+    if (row < nrows) {
+        const int t = (int)(row % ntx);
+        const long long jk = row / ntx;
+        const int j = (int)(jk % (g.ny + 1)), k = (int)(jk / (g.ny + 1));
+        const int i = t * RW + lane;
+        if (i <= g.nx) {
+            const long long o = g.idx(i, j, k);
+            for (int s = 0; s < 6; ++s)
+                if (a[s * g.NP + o] != 0.0) bits |= 1 << s;
+        }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
-    if (lane == 0) rows[row] = (uint8_t)bits;
+    for (int off = RW / 2; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
+    if (lane == 0 && row < nrows) rows[row] = (uint8_t)bits;
 }
 
 }  // namespace
@@ -1072,7 +1076,7 @@ void launch_tiles(const Geo& g, const double* a, int* flags, int* list, int* cou
 }
 
 void fused_tile_dims(const Geo& g, int& ntx, int& nty, int& ntz) {
-    ntx = (g.nx + 1 + TX - 1) / TX - (fused_fold(g.nx) ? 1 : 0);
+    ntx = (g.nx + 1 + FTX - 1) / FTX - (fused_fold(g.nx) ? 1 : 0);
     nty = (g.ny + 1 + FTY - 1) / FTY;
     ntz = (g.nz + 1 + FKZ - 1) / FKZ;
 }
@@ -1089,17 +1093,16 @@ void launch_fused_tiles(const Geo& g, const int* tile_flags, int* flags, int* li
 }
 
 long long row_bytes(const Geo& g) {
-    int ntx, nty, ntz;
-    tile_dims(g, ntx, nty, ntz);
-    return (long long)ntx * (g.ny + 1) * (g.nz + 1);
+    const int rntx = (g.nx + kRow3X) / kRow3X;
+    return (long long)rntx * (g.ny + 1) * (g.nz + 1);
 }
 
 void launch_row_bits(const Geo& g, const double* a, uint8_t* rows, hipStream_t s) {
-    int ntx, nty, ntz;
-    tile_dims(g, ntx, nty, ntz);
+    const int rntx = (g.nx + kRow3X) / kRow3X;
     const long long n = row_bytes(g);
-    hipLaunchKernelGGL(k_row_bits, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, g, ntx, a, rows,
-                       n);
+    const long long per = 256 / kRow3X;   // rows per workgroup
+    hipLaunchKernelGGL(k_row_bits, dim3((unsigned)((n + per - 1) / per)), dim3(256), 0, s, g, rntx,
+                       a, rows, n);
 }
 
 // Workgroups of a 3D apply launch: no more than can be resident at once
@@ -1148,10 +1151,10 @@ int tile_split(int count, int capacity) {
     return split;
 }
 
-// the same for the fused work tiles (at most FKZ / 4 parts of 4 planes)
+// the same rule for the fused work tiles (at most FKZ parts)
 int fused_split(int count, int capacity) {
     int split = 1;
-    while (split < FKZ / 4 && (long long)count * split * 2 <= capacity) split *= 2;
+    while (split < FKZ && (long long)count * split * 2 <= capacity) split *= 2;
     return split;
 }
 

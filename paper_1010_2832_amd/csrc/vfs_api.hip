@@ -504,9 +504,28 @@ int solve_schwarz(vfs_ctx* ctx, const double* b, double* x) {
     double* p = ctx->p0;
     double* q = ctx->q;
     const RedArgs none{ctx->sc + 2, nullptr, 0, nullptr, 0, 0};
+    // 3D: the vector kernels sweep the rows holding an active sample
+    RowList rl{nullptr, -1};
+    if (g.dim == 3) {
+        if (ctx->rowlist_n < 0) {
+            if (!ctx->rowlist) {
+                if (hipMalloc((void**)&ctx->rowlist, (size_t)row_items(g) * sizeof(int)) !=
+                        hipSuccess ||
+                    hipMalloc((void**)&ctx->rowlist_cnt,
+                              (size_t)(row_list_chunks(g) + 1) * sizeof(int)) != hipSuccess)
+                    return fail(ctx, VFS_ENOMEM, "hipMalloc failed (row list)");
+            }
+            launch_row_list(g, ctx->rowbits, ctx->rowlist, ctx->rowlist_cnt, s);
+            HIPCHK(hipMemcpyAsync(ctx->tile_count_host + 2, ctx->rowlist_cnt + row_list_chunks(g),
+                                  sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ctx->rowlist_n = ctx->tile_count_host[2];
+        }
+        rl = RowList{ctx->rowlist, ctx->rowlist_n};
+    }
     HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
     HIPCHK(hipMemcpyAsync(r, b, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    launch_pcg_dot(g, r, r, part, nullptr, s);
+    launch_pcg_dot(g, rl, r, r, part, nullptr, s);
     launch_pcg_start(part, nb, S, ctx->tol, ctx->max_iter, false, s);
     HIPCHK(hipGetLastError());
     int total = 0, outer = 0, status = VFS_OK;
@@ -518,17 +537,18 @@ int solve_schwarz(vfs_ctx* ctx, const double* b, double* x) {
             for (int k = 0; k < chunk; ++k) {
                 const bool timed = ctx->prof && k == 0;
                 if (timed) HIPCHK(hipEventRecord(ctx->pev[3], s));
-                launch_schwarz(g, overlap, r, ctx->a, ctx->c, ctx->dinv, ctx->K, z, done, s);
+                launch_schwarz(g, overlap, r, ctx->a, ctx->c, ctx->dinv, ctx->K, ctx->rowbits, z,
+                               done, s);
                 if (timed) HIPCHK(hipEventRecord(ctx->pev[0], s));
-                launch_pcg_dot(g, r, z, part, done, s);
+                launch_pcg_dot(g, rl, r, z, part, done, s);
                 launch_pcg_rz(part, nb, S, s);
-                launch_pcg_dir(g, z, p, S, s);
+                launch_pcg_dir(g, rl, z, p, S, s);
                 launch_apply<double>(g, ctx->tiles, MODE_APPLY, false, nullptr, nullptr, nullptr, p,
                                      nullptr, q, ctx->a, ctx->c, ctx->K, nullptr, none, s);
-                launch_pcg_dot(g, p, q, part, done, s);
+                launch_pcg_dot(g, rl, p, q, part, done, s);
                 launch_pcg_pq(part, nb, S, s);
                 if (timed) HIPCHK(hipEventRecord(ctx->pev[1], s));
-                launch_pcg_update(g, x, r, p, q, S, part, s);
+                launch_pcg_update(g, rl, x, r, p, q, S, part, s);
                 launch_pcg_check(part, nb, S, s);
                 if (timed) HIPCHK(hipEventRecord(ctx->pev[2], s));
             }
@@ -564,7 +584,7 @@ int solve_schwarz(vfs_ctx* ctx, const double* b, double* x) {
             status = VFS_ENOTCONV;
             break;
         }
-        launch_pcg_dot(g, r, r, part, nullptr, s);
+        launch_pcg_dot(g, rl, r, r, part, nullptr, s);
         launch_pcg_start(part, nb, S, ctx->tol, ctx->max_iter - total, true, s);
         HIPCHK(hipGetLastError());
     }
@@ -648,6 +668,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         launch_fused_tiles(g, ctx->tile_flags, ctx->ftile_flags, ctx->ftile_list,
                            ctx->tile_count + 1, s);
         launch_row_bits(g, ctx->a, ctx->rowbits, s);
+        ctx->rowlist_n = -1;   // the row list follows the new row bits
         HIPCHK(hipMemcpyAsync(ctx->tile_count_host, ctx->tile_count, 2 * sizeof(int),
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -804,6 +825,8 @@ int vfs_destroy(vfs_ctx* ctx) {
     if (ctx->ftile_flags) (void)hipFree(ctx->ftile_flags);
     if (ctx->ftile_list) (void)hipFree(ctx->ftile_list);
     if (ctx->rowbits) (void)hipFree(ctx->rowbits);
+    if (ctx->rowlist) (void)hipFree(ctx->rowlist);
+    if (ctx->rowlist_cnt) (void)hipFree(ctx->rowlist_cnt);
     if (ctx->tile_count_host) (void)hipHostFree(ctx->tile_count_host);
     if (ctx->sc_host) (void)hipHostFree(ctx->sc_host);
     if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);

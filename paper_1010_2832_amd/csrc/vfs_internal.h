@@ -31,18 +31,25 @@ constexpr int kFront = 16;
 constexpr int kMaxTileBlocks = 1536;
 // 3D tile: 64 x 4 anchors in x, y, marching 8 planes in z
 constexpr int kTile3X = 64, kTile3Y = 4, kTile3Z = 8;
-// Work tile of the fused 3D CG iteration: 64 x kFused3Y anchors marching
-// kFused3Z planes, a whole number of the tiles above in y and z (fewer halo
-// rows and planes per anchor than one tile).
+// Work tile of the fused 3D CG iteration: kFused3X x kFused3Y anchors
+// marching kFused3Z planes, one thread per anchor of a plane; in y and z a
+// whole number of the tiles above, in x a part of one.  The row bits of the
+// 3D solve (one byte per kFused3X-anchor row) share its x width.
+#ifndef VFS_FUSED3_X
+#define VFS_FUSED3_X 64
+#endif
 #ifndef VFS_FUSED3_Y
 #define VFS_FUSED3_Y 4
 #endif
 #ifndef VFS_FUSED3_Z
 #define VFS_FUSED3_Z 8
 #endif
-constexpr int kFused3Y = VFS_FUSED3_Y, kFused3Z = VFS_FUSED3_Z;
-static_assert(kFused3Y % kTile3Y == 0 && kFused3Z % kTile3Z == 0 && kFused3Y <= 16,
-              "a fused tile holds whole tiles and at most 1024 threads");
+constexpr int kFused3X = VFS_FUSED3_X, kFused3Y = VFS_FUSED3_Y, kFused3Z = VFS_FUSED3_Z;
+constexpr int kRow3X = kFused3X;
+static_assert(kTile3X % kFused3X == 0 && kFused3X >= 16 && kFused3Y % kTile3Y == 0 &&
+                  kFused3Z % kTile3Z == 0 && kFused3X * kFused3Y <= 1024 &&
+                  (kFused3X * kFused3Y) % 64 == 0,
+              "a fused tile holds whole tiles in y, z and whole waves");
 
 struct Geo {
     int dim;
@@ -252,12 +259,17 @@ struct vfs_ctx {
     vfs::Tiles tiles{nullptr, 0, 0, 0, 0};
     int tiles2d = 0;                 // 2D: active tiles of the fused CG (in tile_list)
     // 3D: work tiles of the fused iteration holding an active tile, and one
-    // byte per 64-anchor row (x tile, y, z) with bit s set if sample slice s
-    // has an active sample in the row
+    // byte per kRow3X-anchor row (x part, y, z) with bit s set if sample slice
+    // s has an active sample in the row
     int* ftile_flags = nullptr;
     int* ftile_list = nullptr;
     vfs::Tiles ftiles{nullptr, 0, 0, 0, 0};
     uint8_t* rowbits = nullptr;
+    // the (slice, row) items of the set row bits, built on the first FP64
+    // brick-preconditioned solve after an assembly (launch_row_list)
+    int* rowlist = nullptr;
+    int* rowlist_cnt = nullptr;
+    int rowlist_n = -1;            // -1: to be built
 
     bool assembled = false;
     double dt_assembled = 0.0;
@@ -336,21 +348,34 @@ void launch_advect_phi(const Geo& g, double dt, const double* uext, const double
                        hipStream_t s);
 
 // brick-local Schwarz / block symmetric Gauss-Seidel preconditioner and the
-// FP64 PCG around it (k_schwarz.hip)
+// FP64 PCG around it (k_schwarz.hip); rows: the 3D row bits (bricks whose rows
+// hold no active sample are skipped), ignored in 2D.  The PCG vector kernels
+// sweep, in 3D, the compacted list of (slice, row) items whose row bit is set
+// (RowList, built by launch_row_list: item u = slice * row_bytes + row, the
+// count of cnt[row_list_chunks] after the build) and, in 2D (count < 0), the
+// whole arrays.
+struct RowList {
+    const int* list;
+    int count;
+};
+long long row_items(const Geo& g);
+int row_list_chunks(const Geo& g);
+void launch_row_list(const Geo& g, const uint8_t* rows, int* list, int* cnt, hipStream_t st);
 int schwarz_brick(int dim, int overlap);
 void launch_schwarz(const Geo& g, int overlap, const double* r, const double* a, const double* c,
-                    const double* dinv, const double* K, double* z, const int* done,
-                    hipStream_t st);
+                    const double* dinv, const double* K, const uint8_t* rows, double* z,
+                    const int* done, hipStream_t st);
 int pcg_blocks(const Geo& g);
-void launch_pcg_dot(const Geo& g, const double* u, const double* v, double* part, const int* done,
-                    hipStream_t st);
+void launch_pcg_dot(const Geo& g, const RowList& rl, const double* u, const double* v,
+                    double* part, const int* done, hipStream_t st);
 void launch_pcg_start(const double* part, int nb, Scalars* S, double tol, int max_iter,
                       bool keep_bb, hipStream_t st);
 void launch_pcg_rz(const double* part, int nb, Scalars* S, hipStream_t st);
-void launch_pcg_dir(const Geo& g, const double* z, double* p, const Scalars* S, hipStream_t st);
+void launch_pcg_dir(const Geo& g, const RowList& rl, const double* z, double* p,
+                    const Scalars* S, hipStream_t st);
 void launch_pcg_pq(const double* part, int nb, Scalars* S, hipStream_t st);
-void launch_pcg_update(const Geo& g, double* x, double* r, const double* p, const double* q,
-                       const Scalars* S, double* part, hipStream_t st);
+void launch_pcg_update(const Geo& g, const RowList& rl, double* x, double* r, const double* p,
+                       const double* q, const Scalars* S, double* part, hipStream_t st);
 void launch_pcg_check(const double* part, int nb, Scalars* S, hipStream_t st);
 
 // packing and checks (k_util.hip)

@@ -615,7 +615,7 @@ int vfs_precond_apply(vfs_ctx* ctx, const double* r, double* z) {
         if (rc) return rc;
         launch_mask(ctx->r, ctx->q, ctx->a, n, ctx->stream);
         launch_schwarz(g, ctx->precond == VFS_PRECOND_SCHWARZ ? 1 : 0, ctx->r, ctx->a, ctx->c,
-                       ctx->dinv, ctx->K, ctx->z, nullptr, ctx->stream);
+                       ctx->dinv, ctx->K, ctx->rowbits, ctx->z, nullptr, ctx->stream);
         if (hipGetLastError() != hipSuccess) return ctx_fail(ctx, VFS_EHIP, "launch failed");
         return ctx_get_samples(ctx, ctx->z, z);
     }
