@@ -575,6 +575,7 @@ __device__ __forceinline__ void fused_origin(const Tiles& t, const Geo& g, int u
 template <typename T>
 struct FusedOwn {
     T r[6], q[6], p[6], d[6], a[6], x[6];
+    T c[5];       // compliance coefficients of the own anchor one plane below
     unsigned m;   // row bits of the plane
 };
 template <typename T>
@@ -647,6 +648,10 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
     __shared__ T gW[2][FFY][FFX];
     __shared__ T sXF[2][FTY][2][5];     // folded column: p, a, z, D^-1, c per plane parity
     __shared__ unsigned sXM[2][FTY];    // and its row bits
+    // row bits of the work item's planes k0 - 1 .. kend, rows j0 - 1 .. j0 + FTY,
+    // x tiles xt - 1, xt, xt + 1 (read once per item, so that no plane waits
+    // on a global load before it can issue its own)
+    __shared__ uint8_t sRB[FKZ + 2][FHY][3];
     const long long NP = g.NP;
     const int tid = threadIdx.x;
     const int tx = tid % FTX, ty = tid / FTX;
@@ -680,13 +685,27 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
         const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
         // this thread also owns anchor (nx, jh) of the folded column
         const bool xown = xrole && xt == ft.ntx - 1 && jh <= g.ny;
+        __syncthreads();   // LDS of the previous item is no longer read
+        for (int e = tid; e < (kend - k0 + 2) * FHY * 3; e += FNT) {
+            const int pl = e / (FHY * 3), rw = (e / 3) % FHY, part = e % 3;
+            sRB[pl][rw][part] =
+                (uint8_t)row_bits_at(g, rows, rntx, xt + part - 1, j0 - 1 + rw, k0 - 1 + pl);
+        }
 
         auto fetch = [&](int kk, FusedOwn<T>& o, FusedHalo<T>& h) {
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
-            o.m = io <= g.nx + 1 ? row_bits_at(g, rows, rntx, xt, jo, kk) : 0u;
+            const int pl = kk - k0 + 1;
+            o.m = io <= g.nx + 1 ? sRB[pl][ty + 1][1] : 0u;
             const long long oo = o.m ? g.idx(io, jo, kk) : 0;
-            h.m = (hrole && ih <= g.nx + 1) ? row_bits_at(g, rows, rntx, xt + hdt, jh, kk) : 0u;
+            h.m = (hrole && ih <= g.nx + 1) ? sRB[pl][hlj][hdt + 1] : 0u;
             const long long oh = h.m ? g.idx(ih, jh, kk) : 0;
+            // c of the own anchor at plane kk - 1 (the plane whose outputs are
+            // formed while this one is being committed)
+            const bool ownb = io <= g.nx && jo <= g.ny && kk - 1 >= k0 && kk - 1 < kend;
+            const unsigned mb = ownb ? sRB[pl - 1][ty + 1][1] : 0u;
+            const long long ob = mb ? g.idx(io, jo, kk - 1) : 0;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) o.c[s] = ((mb >> (s + 1)) & 1u) ? c[(s + 1) * NP + ob] : T(0);
             const bool hx = xown && kk >= k0 && kk < kend;
             const bool h3 = hx && ((h.m >> 3) & 1u), h4 = hx && ((h.m >> 4) & 1u);
             h.x3 = (h3 && !INIT) ? x[3 * NP + oh] : T(0);
@@ -713,8 +732,10 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
         // r_k, z_k, p_k of plane kk into the ring slot; own anchors also store
         // r_k, x_k, p_k and add to r.z, r.r; own p, a, z, D^-1 and row bits out
         auto commit = [&](int kk, const FusedOwn<T>& o, const FusedHalo<T>& h, T (&vo)[6],
-                          T (&ao)[6], T (&zo)[6], T (&dq)[6], unsigned& mo) {
+                          T (&ao)[6], T (&zo)[6], T (&dq)[6], unsigned& mo, T (&cb)[5]) {
             const int sl = kk & 1;
+#pragma unroll
+            for (int s = 0; s < 5; ++s) cb[s] = o.c[s];
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
             const long long oo = own ? g.idx(io, jo, kk) : 0;
             mo = own ? o.m : 0u;
@@ -820,39 +841,31 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                                           (sW[s1][5][lj][li] - sW[s1][5][lj + 1][li]));
             }
         };
-        // compliance coefficients of the own anchor of plane kk (row bits m)
-        auto fetchC = [&](int kk, unsigned m, T (&cc)[5]) {
-            const long long o = m ? g.idx(io, jo, kk) : 0;
-#pragma unroll
-            for (int s = 0; s < 5; ++s) cc[s] = ((m >> (s + 1)) & 1u) ? c[(s + 1) * NP + o] : T(0);
-        };
 
         T vcur[6], acur[6], zcur[6], dcur[6], vnext[6], anext[6], znext[6], dnext[6];
         unsigned mcur, mnext;
         FusedOwn<T> Fo;
         FusedHalo<T> Fh;
         T Ku[NF], Kv[NF], Kw[NF], Cc[5];
-        __syncthreads();   // LDS of the previous tile is no longer read
+        __syncthreads();   // row bits of this item in LDS
         fetch(k0 - 1, Fo, Fh);
         fetchK(k0 - 1, Ku, Kv, Kw);
-        commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext, mnext);
+        commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext, mnext, Cc);
         fetch(k0, Fo, Fh);
-        commit(k0, Fo, Fh, vcur, acur, zcur, dcur, mcur);
+        commit(k0, Fo, Fh, vcur, acur, zcur, dcur, mcur, Cc);
         fetch(k0 + 1, Fo, Fh);
         __syncthreads();
         faces(k0 - 1, Ku, Kv, Kw);
         fetchK(k0, Ku, Kv, Kw);
-        fetchC(k0, mcur, Cc);
         __syncthreads();
 
         for (int k = k0; k < kend; ++k) {
-            commit(k + 1, Fo, Fh, vnext, anext, znext, dnext, mnext);
+            // c of plane k arrives with the raw inputs of plane k + 1
+            commit(k + 1, Fo, Fh, vnext, anext, znext, dnext, mnext, Cc);
             if (k + 2 <= kend) fetch(k + 2, Fo, Fh);
             __syncthreads();
             faces(k, Ku, Kv, Kw);
-            T Cn[5];
             fetchK(k + 1, Ku, Kv, Kw);
-            fetchC(k + 1, mnext, Cn);
             __syncthreads();
             if (mcur) {
                 const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;
@@ -910,8 +923,6 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                 dcur[s] = dnext[s];
             }
             mcur = mnext;
-#pragma unroll
-            for (int s = 0; s < 5; ++s) Cc[s] = Cn[s];
         }
     }
     double vv[5] = {rz_n, pq_n, qz_n, qdq_n, rr_n};
