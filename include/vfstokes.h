@@ -280,7 +280,7 @@ int vfs_get_sizes(const vfs_ctx* ctx, int64_t* n_samples, int64_t* n_faces);
  * space is one fixed 96 MiB device array per GPU, held until the process
  * ends: it takes (16 (nx ny [nz]) + 2 nsets NP) doubles, NP the padded grid
  * size of the conventions above, which admits square 2D grids up to 882^2
- * and cubic 3D grids up to 72^3; larger grids return VFS_EINVAL.  Every call on a
+ * and cubic 3D grids up to 69^3; larger grids return VFS_EINVAL.  Every call on a
  * GPU shares that GPU's array, so calls that overlap in time on one GPU
  * (different streams or threads) race and must be serialised by the caller.
  * Errors: VFS_EINVAL (sizes, set, w_min, NULL pointers), VFS_EHIP; the

@@ -530,9 +530,15 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
 // tile in x, FTY / 4 x FKZ / 8 list tiles in y and z), so the halo ring costs
 // 2 rows per FTY, 2 columns per FTX and 2 planes per FKZ.  Every solver vector
 // is zero on a sample with a = 0 (inactive samples have a = c = D^-1 = 0, the
-// solve starts from zero there and nothing is ever stored there), so an
-// FTX-wide row of one sample slice whose row bit is clear is neither loaded
-// nor stored: its values are known to be 0.
+// solve starts from zero there and nothing is ever stored there), so a half
+// row of one sample slice whose row bit is clear is neither loaded nor
+// stored: its values are known to be 0.
+//
+// The direction is kept weighted, P = a p (a = W_L), and the preconditioner
+// as e = a D^-1 (ad): the faces need a p_k = e r_k + beta P_{k-1} at every
+// position of the tile and its halo, which takes r, q, P and e (four loads
+// instead of five); the own anchors also read a and form p = P / a and
+// D^-1 = e / a for the update, the partials and the compliance term.
 //
 // When nx is a multiple of FTX the anchors i = 0..nx need one x tile more than
 // nx / FTX, and that tile holds only the column i = nx, where only tau_xy and
@@ -553,10 +559,15 @@ __host__ __device__ __forceinline__ bool fused_fold(int nx) {
 }
 
 // row bits of x tile t, row (j, k); 0 outside the anchors of the grid
-__device__ __forceinline__ unsigned row_bits_at(const Geo& g, const uint8_t* __restrict__ rows,
+__device__ __forceinline__ unsigned row_bits_at(const Geo& g, const RowBits* __restrict__ rows,
                                                 int ntx, int t, int j, int k) {
     if (t < 0 || t >= ntx || j < 0 || j > g.ny || k < 0 || k > g.nz) return 0u;
     return rows[t + (long long)ntx * (j + (long long)(g.ny + 1) * k)];
+}
+
+// slice bits of the half row holding anchor `lane` (0 .. kRow3X - 1) of a row
+__device__ __forceinline__ unsigned half_bits(unsigned rb, int lane) {
+    return (lane >= kRow3X / 2 ? rb >> 6 : rb) & 63u;
 }
 
 // Anchors of fused work item u: x from i0, y from j0, planes [k0, kend).
@@ -574,24 +585,24 @@ __device__ __forceinline__ void fused_origin(const Tiles& t, const Geo& g, int u
 
 template <typename T>
 struct FusedOwn {
-    T r[6], q[6], p[6], d[6], a[6], x[6];
+    T r[6], q[6], P[6], e[6], a[6], x[6];   // P = a p, e = a D^-1
     T c[5];       // compliance coefficients of the own anchor one plane below
     unsigned m;   // row bits of the plane
 };
 template <typename T>
 struct FusedHalo {
-    T r[6], q[6], p[6], d[6], a[6];
-    T x3, x4, c3, c4;   // x and c of tau_xy, tau_xz in the folded column i = nx
+    T r[6], q[6], P[6], e[6];
+    T x3, x4, c3, c4, a3, a4;   // x, c and a of tau_xy, tau_xz in the folded column i = nx
     unsigned m;
 };
 
 template <typename T, bool INIT>
 __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
-                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ ead,
                                                  const T* __restrict__ a,
                                                  const T* __restrict__ c,
                                                  const T* __restrict__ K,
-                                                 const uint8_t* __restrict__ rows, RedArgs ra) {
+                                                 const RowBits* __restrict__ rows, RedArgs ra) {
     Scalars* sc = ra.sc;
     const int kidx = ra.kidx;
     const int pin = (kidx + 1) & 1, pout = kidx & 1;   // launch k reads (k-1)&1, writes k&1
@@ -651,7 +662,7 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
     // row bits of the work item's planes k0 - 1 .. kend, rows j0 - 1 .. j0 + FTY,
     // x tiles xt - 1, xt, xt + 1 (read once per item, so that no plane waits
     // on a global load before it can issue its own)
-    __shared__ uint8_t sRB[FKZ + 2][FHY][3];
+    __shared__ RowBits sRB[FKZ + 2][FHY][3];
     const long long NP = g.NP;
     const int tid = threadIdx.x;
     const int tx = tid % FTX, ty = tid / FTX;
@@ -668,8 +679,10 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
         hlj = 1 + (e >> 1);
         hli = (e & 1) ? FHX - 1 : 0;
     }
-    // x tile of the halo position relative to the work tile's (-1, 0, +1)
+    // x tile of the halo position relative to the work tile's (-1, 0, +1),
+    // and its anchor within that tile's rows
     const int hdt = hli == 0 ? -1 : (hli == FHX - 1 ? 1 : 0);
+    const int hlane = hdt < 0 ? FTX - 1 : (hdt > 0 ? 0 : hli - 1);
     const int rntx = (g.nx + kRow3X) / kRow3X;   // x parts of the row bits
     const bool fold = fused_fold(g.nx);
     // right x-halo threads of the own rows: owners of the folded column
@@ -689,20 +702,20 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
         for (int e = tid; e < (kend - k0 + 2) * FHY * 3; e += FNT) {
             const int pl = e / (FHY * 3), rw = (e / 3) % FHY, part = e % 3;
             sRB[pl][rw][part] =
-                (uint8_t)row_bits_at(g, rows, rntx, xt + part - 1, j0 - 1 + rw, k0 - 1 + pl);
+                (RowBits)row_bits_at(g, rows, rntx, xt + part - 1, j0 - 1 + rw, k0 - 1 + pl);
         }
 
         auto fetch = [&](int kk, FusedOwn<T>& o, FusedHalo<T>& h) {
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
             const int pl = kk - k0 + 1;
-            o.m = io <= g.nx + 1 ? sRB[pl][ty + 1][1] : 0u;
+            o.m = io <= g.nx + 1 ? half_bits(sRB[pl][ty + 1][1], tx) : 0u;
             const long long oo = o.m ? g.idx(io, jo, kk) : 0;
-            h.m = (hrole && ih <= g.nx + 1) ? sRB[pl][hlj][hdt + 1] : 0u;
+            h.m = (hrole && ih <= g.nx + 1) ? half_bits(sRB[pl][hlj][hdt + 1], hlane) : 0u;
             const long long oh = h.m ? g.idx(ih, jh, kk) : 0;
             // c of the own anchor at plane kk - 1 (the plane whose outputs are
             // formed while this one is being committed)
             const bool ownb = io <= g.nx && jo <= g.ny && kk - 1 >= k0 && kk - 1 < kend;
-            const unsigned mb = ownb ? sRB[pl - 1][ty + 1][1] : 0u;
+            const unsigned mb = ownb ? half_bits(sRB[pl - 1][ty + 1][1], tx) : 0u;
             const long long ob = mb ? g.idx(io, jo, kk - 1) : 0;
 #pragma unroll
             for (int s = 0; s < 5; ++s) o.c[s] = ((mb >> (s + 1)) & 1u) ? c[(s + 1) * NP + ob] : T(0);
@@ -712,21 +725,22 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
             h.x4 = (h4 && !INIT) ? x[4 * NP + oh] : T(0);
             h.c3 = h3 ? c[3 * NP + oh] : T(0);
             h.c4 = h4 ? c[4 * NP + oh] : T(0);
+            h.a3 = h3 ? a[3 * NP + oh] : T(0);
+            h.a4 = h4 ? a[4 * NP + oh] : T(0);
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
                 const long long so = oo + s * NP, sh = oh + s * NP;
                 const bool lo = (o.m >> s) & 1u, lh = (h.m >> s) & 1u;
                 o.r[s] = lo ? r_in[so] : T(0);
-                o.d[s] = lo ? dinv[so] : T(0);
+                o.e[s] = lo ? ead[so] : T(0);
                 o.a[s] = lo ? a[so] : T(0);
                 o.q[s] = (lo && !INIT) ? q_in[so] : T(0);
-                o.p[s] = (lo && !INIT) ? p_in[so] : T(0);
+                o.P[s] = (lo && !INIT) ? p_in[so] : T(0);
                 o.x[s] = (lo && own && !INIT) ? x[so] : T(0);
                 h.r[s] = lh ? r_in[sh] : T(0);
-                h.d[s] = lh ? dinv[sh] : T(0);
-                h.a[s] = lh ? a[sh] : T(0);
+                h.e[s] = lh ? ead[sh] : T(0);
                 h.q[s] = (lh && !INIT) ? q_in[sh] : T(0);
-                h.p[s] = (lh && !INIT) ? p_in[sh] : T(0);
+                h.P[s] = (lh && !INIT) ? p_in[sh] : T(0);
             }
         };
         // r_k, z_k, p_k of plane kk into the ring slot; own anchors also store
@@ -742,31 +756,31 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
                 const T rn = INIT ? o.r[s] : o.r[s] - alpha * o.q[s];
-                const T zn = o.d[s] * rn;
-                const T pn = INIT ? zn : zn + beta * o.p[s];
+                const T W = INIT ? o.e[s] * rn : o.e[s] * rn + beta * o.P[s];   // a p_k
+                const T ia = o.a[s] != T(0) ? T(1) / o.a[s] : T(0);
+                const T dd = o.e[s] * ia;   // D^-1
+                const T zn = dd * rn;
                 if ((mo >> s) & 1u) {
                     const long long os = oo + s * NP;
                     if (!INIT) {
                         r_out[os] = rn;
-                        x[os] = o.x[s] + alpha * o.p[s];
+                        x[os] = o.x[s] + alpha * (o.P[s] * ia);
                     }
-                    p_out[os] = pn;
+                    p_out[os] = W;
                     rz_n += (double)rn * (double)zn;
                     rr_n += (double)rn * (double)rn;
                 }
-                vo[s] = pn;
+                vo[s] = W * ia;
                 ao[s] = o.a[s];
                 zo[s] = zn;
-                dq[s] = o.d[s];
-                sW[sl][s][ty + 1][tx + 1] = o.a[s] * pn;
+                dq[s] = dd;
+                sW[sl][s][ty + 1][tx + 1] = W;
             }
             if (hrole) {
 #pragma unroll
                 for (int s = 0; s < 6; ++s) {
                     const T rn = INIT ? h.r[s] : h.r[s] - alpha * h.q[s];
-                    const T zn = h.d[s] * rn;
-                    const T pn = INIT ? zn : zn + beta * h.p[s];
-                    sW[sl][s][hlj][hli] = h.a[s] * pn;
+                    sW[sl][s][hlj][hli] = INIT ? h.e[s] * rn : h.e[s] * rn + beta * h.P[s];
                 }
             }
             // the folded column: tau_xy (slice 3) and tau_xz (slice 4) at
@@ -781,20 +795,23 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                     const int s = 3 + e;
                     if (!((xm >> s) & 1u)) continue;
                     const T rn = INIT ? h.r[s] : h.r[s] - alpha * h.q[s];
-                    const T zn = h.d[s] * rn;
-                    const T pn = INIT ? zn : zn + beta * h.p[s];
+                    const T W = INIT ? h.e[s] * rn : h.e[s] * rn + beta * h.P[s];
+                    const T as = e ? h.a4 : h.a3;
+                    const T ia = as != T(0) ? T(1) / as : T(0);
+                    const T dd = h.e[s] * ia;
+                    const T zn = dd * rn;
                     T* f = sXF[sl][hlj - 1][e];
-                    f[0] = pn;
-                    f[1] = h.a[s];
+                    f[0] = W * ia;
+                    f[1] = as;
                     f[2] = zn;
-                    f[3] = h.d[s];
+                    f[3] = dd;
                     f[4] = e ? h.c4 : h.c3;
                     const long long os = oh + s * NP;
                     if (!INIT) {
                         r_out[os] = rn;
-                        x[os] = (e ? h.x4 : h.x3) + alpha * h.p[s];
+                        x[os] = (e ? h.x4 : h.x3) + alpha * (h.P[s] * ia);
                     }
-                    p_out[os] = pn;
+                    p_out[os] = W;
                     rz_n += (double)rn * (double)zn;
                     rr_n += (double)rn * (double)rn;
                 }
@@ -1045,10 +1062,11 @@ __global__ void k_fused_flags(int ntx, int nty, int ntz, int fnx, int fny, int f
     fflags[id] = any ? 1 : 0;
 }
 
-// kRow3X lanes per row (x part t, y, z): bit s of the row's byte is set if
-// an anchor i = RW t .. RW t + RW - 1 (i <= nx) has a != 0 in sample slice s.
+// kRow3X lanes per row (x part t, y, z): bit s (bit 6 + s) of the row's word
+// is set if an anchor i <= nx of the first (second) half of RW t .. RW t +
+// RW - 1 has a != 0 in sample slice s.
 __global__ __launch_bounds__(256) void k_row_bits(Geo g, int ntx, const double* __restrict__ a,
-                                                  uint8_t* __restrict__ rows, long long nrows) {
+                                                  RowBits* __restrict__ rows, long long nrows) {
     constexpr int RW = kRow3X;
     const long long row = ((long long)blockIdx.x * 256 + threadIdx.x) / RW;
     const int lane = threadIdx.x % RW;
@@ -1065,8 +1083,9 @@ __global__ __launch_bounds__(256) void k_row_bits(Geo g, int ntx, const double* 
         }
     }
 #pragma unroll
-    for (int off = RW / 2; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);
-    if (lane == 0 && row < nrows) rows[row] = (uint8_t)bits;
+    for (int off = RW / 4; off > 0; off >>= 1) bits |= __shfl_xor(bits, off);   // each half
+    const int other = __shfl_xor(bits, RW / 2);   // the other half's bits
+    if (lane == 0 && row < nrows) rows[row] = (RowBits)(bits | (other << 6));
 }
 
 }  // namespace
@@ -1108,7 +1127,7 @@ long long row_bytes(const Geo& g) {
     return (long long)rntx * (g.ny + 1) * (g.nz + 1);
 }
 
-void launch_row_bits(const Geo& g, const double* a, uint8_t* rows, hipStream_t s) {
+void launch_row_bits(const Geo& g, const double* a, RowBits* rows, hipStream_t s) {
     const int rntx = (g.nx + kRow3X) / kRow3X;
     const long long n = row_bytes(g);
     const long long per = 256 / kRow3X;   // rows per workgroup
@@ -1203,15 +1222,15 @@ int fused3d_grid(int count) {
 }
 
 void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v,
-                    const float* dinv, const float* a, const float* c, const float* K,
-                    const uint8_t* rows, const RedArgs& ra, hipStream_t s) {
+                    const float* ead, const float* a, const float* c, const float* K,
+                    const RowBits* rows, const RedArgs& ra, hipStream_t s) {
     if (ft.count <= 0) return;
     const dim3 gs(fused3d_grid(ft.items()));
     if (init)
-        hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(FNT), 0, s, g, ft, v, dinv, a, c, K,
+        hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(FNT), 0, s, g, ft, v, ead, a, c, K,
                            rows, ra);
     else
-        hipLaunchKernelGGL((k_fused3d<float, false>), gs, dim3(FNT), 0, s, g, ft, v, dinv, a, c, K,
+        hipLaunchKernelGGL((k_fused3d<float, false>), gs, dim3(FNT), 0, s, g, ft, v, ead, a, c, K,
                            rows, ra);
 }
 

@@ -88,7 +88,7 @@ struct SgsArgs {
     int cls[3];       // brick class of this launch (parity per axis), -1: every brick
     int accumulate;   // z += correction (overlapping bricks) or z = correction
     const int* done;  // skip when set (a converged solve)
-    const uint8_t* rows;   // 3D row bits (active sample slices per 64-anchor row) or null
+    const RowBits* rows;   // 3D row bits (active sample slices per row half) or null
     int rntx;              // x tiles of the row bits
 };
 
@@ -290,13 +290,14 @@ __device__ __forceinline__ void pcg_sweep(const Geo& g, const RowList& rl, F f) 
 // product over it, runs in the same order on every call).
 constexpr int RL_PER = 16, RL_CHUNK = NT * RL_PER;
 
-__device__ __forceinline__ bool row_item(const uint8_t* __restrict__ rows, long long nrow,
+__device__ __forceinline__ bool row_item(const RowBits* __restrict__ rows, long long nrow,
                                          long long u) {
     const int s = (int)(u / nrow);
-    return (rows[u - s * nrow] >> s) & 1u;
+    const unsigned rb = rows[u - s * nrow];
+    return ((rb | (rb >> 6)) >> s) & 1u;
 }
 
-__global__ __launch_bounds__(NT) void k_rl_count(const uint8_t* __restrict__ rows, long long nrow,
+__global__ __launch_bounds__(NT) void k_rl_count(const RowBits* __restrict__ rows, long long nrow,
                                                  long long n, int* __restrict__ cnt) {
     const long long base = (long long)blockIdx.x * RL_CHUNK + (long long)threadIdx.x * RL_PER;
     int c = 0;
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(1024) void k_rl_scan(int* __restrict__ cnt, int nch
     }
 }
 
-__global__ __launch_bounds__(NT) void k_rl_write(const uint8_t* __restrict__ rows, long long nrow,
+__global__ __launch_bounds__(NT) void k_rl_write(const RowBits* __restrict__ rows, long long nrow,
                                                  long long n, const int* __restrict__ off,
                                                  int* __restrict__ list) {
     const long long base = (long long)blockIdx.x * RL_CHUNK + (long long)threadIdx.x * RL_PER;
@@ -510,7 +511,7 @@ int schwarz_brick(int dim, int overlap) {
 }
 
 void launch_schwarz(const Geo& g, int overlap, const double* r, const double* a, const double* c,
-                    const double* dinv, const double* K, const uint8_t* rows, double* z,
+                    const double* dinv, const double* K, const RowBits* rows, double* z,
                     const int* done, hipStream_t st) {
     SgsArgs s{};
     s.rows = g.dim == 3 ? rows : nullptr;
@@ -567,7 +568,7 @@ long long row_items(const Geo& g) { return row_bytes(g) * g.nsamp(); }
 
 int row_list_chunks(const Geo& g) { return (int)((row_items(g) + RL_CHUNK - 1) / RL_CHUNK); }
 
-void launch_row_list(const Geo& g, const uint8_t* rows, int* list, int* cnt, hipStream_t st) {
+void launch_row_list(const Geo& g, const RowBits* rows, int* list, int* cnt, hipStream_t st) {
     const long long nrow = row_bytes(g), n = row_items(g);
     const int nchunk = row_list_chunks(g);
     hipLaunchKernelGGL(k_rl_count, dim3(nchunk), dim3(NT), 0, st, rows, nrow, n, cnt);

@@ -67,6 +67,13 @@ __global__ void k_to_f32(const double* __restrict__ s, float* __restrict__ d, lo
     if (t < n) d[t] = (float)s[t];
 }
 
+// d = (float)(u v), the product rounded once
+__global__ void k_mul_to_f32(const double* __restrict__ u, const double* __restrict__ v,
+                             float* __restrict__ d, long long n) {
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) d[t] = (float)(u[t] * v[t]);
+}
+
 __global__ void k_mask(double* __restrict__ d, const double* __restrict__ s,
                        const double* __restrict__ a, long long n) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -121,6 +128,11 @@ void launch_zero_box_faces(const Geo& g, double* faces, hipStream_t s) {
 void launch_to_f32(const double* src, float* dst, long long n, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+
+void launch_mul_to_f32(const double* u, const double* v, float* dst, long long n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_mul_to_f32, dim3(nblk(n, 256)), dim3(256), 0, s, u, v, dst, n);
 }
 
 void launch_mask(double* dst, const double* src, const double* a, long long n, hipStream_t s) {

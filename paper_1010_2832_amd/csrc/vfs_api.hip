@@ -230,7 +230,7 @@ int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)kMaxTileBlocks + 32};
     const FusedVecs fv{ctx->x32, {ctx->r32, ctx->z32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
     const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
-    launch_fused3d(g, ctx->ftiles, true, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32,
+    launch_fused3d(g, ctx->ftiles, true, fv, ctx->ead32, ctx->a32, ctx->c32, ctx->K32,
                    ctx->rowbits, r0, s);
     int chunk = 8;
     int kidx = 1;
@@ -239,7 +239,7 @@ int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
             const RedArgs ra{ctx->sc, part[(kidx + 1) & 1], nb, part[kidx & 1], kidx,
                              (set_bb && kidx == 1) ? 1 : 0};
             if (ctx->prof && k == 1) HIPCHK(hipEventRecord(ctx->pev[0], s));
-            launch_fused3d(g, ctx->ftiles, false, fv, ctx->dinv32, ctx->a32, ctx->c32, ctx->K32,
+            launch_fused3d(g, ctx->ftiles, false, fv, ctx->ead32, ctx->a32, ctx->c32, ctx->K32,
                            ctx->rowbits, ra, s);
         }
         if (ctx->prof) HIPCHK(hipEventRecord(ctx->pev[1], s));
@@ -690,6 +690,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         launch_to_f32(ctx->a, ctx->a32, ns, s);
         launch_to_f32(ctx->c, ctx->c32, ns, s);
         launch_to_f32(ctx->dinv, ctx->dinv32, ns, s);
+        if (g.dim == 3) launch_mul_to_f32(ctx->a, ctx->dinv, ctx->ead32, ns, s);
     }
     HIPCHK(hipGetLastError());
     ctx->assembled = true;
@@ -765,11 +766,16 @@ Geo make_geo(int dim, int nx, int ny, int nz, double h) {
     g.nx = nx;
     g.ny = ny;
     g.nz = dim == 3 ? nz : 1;
-    g.PX = ((nx + 3) + 15) / 16 * 16;
+    // 3D: rows of 32-element multiples after a 32-element front, slices of
+    // 32-element multiples, so every row starts on a 128-byte line in FP32 and
+    // each half of a 64-anchor row (the unit of the row bits) is one line; 2D
+    // rows stay 16-element multiples (64-byte aligned)
+    const int ra = dim == 3 ? 32 : 16;
+    g.PX = ((nx + 3) + ra - 1) / ra * ra;
     g.PY = ny + 3;
     g.PZ = dim == 3 ? nz + 3 : 1;
     const long long body = (long long)g.PX * g.PY * g.PZ;
-    g.NP = (kFront + body + 16 + 15) / 16 * 16;
+    g.NP = (kFront + body + 32 + 31) / 32 * 32;
     g.h = h;
     return g;
 }
@@ -815,7 +821,7 @@ int vfs_destroy(vfs_ctx* ctx) {
                     ctx->p032,  ctx->p132,  ctx->q32,  ctx->z32,    ctx->partials, ctx->counter,
                     ctx->sc,    ctx->flag,  ctx->stage, ctx->netvec, ctx->netpart, ctx->netcoef,
                     ctx->f32b,  ctx->fpart, ctx->ybc, ctx->adv_a, ctx->adv_b, ctx->adv_ka,
-                    ctx->adv_kb, ctx->phi_tmp};
+                    ctx->adv_kb, ctx->phi_tmp, ctx->ead32};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (ctx->net_owned) (void)vfs_unet_destroy(ctx->net_owned);
@@ -882,6 +888,7 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
     ALLOC(ctx->a32, ns * NP);
     ALLOC(ctx->c32, ns * NP);
     ALLOC(ctx->dinv32, ns * NP);
+    if (dim == 3) ALLOC(ctx->ead32, ns * NP);
     ALLOC(ctx->x, ns * NP);
     ALLOC(ctx->r, ns * NP);
     ALLOC(ctx->p0, ns * NP);

@@ -25,7 +25,7 @@
 
 namespace vfs {
 
-constexpr int kFront = 16;
+constexpr int kFront = 32;   // elements before the body (128-byte rows, see make_geo)
 // 3D kernels run at most this many workgroups, each looping over tiles, so
 // that the partial sums a consumer must read stay few.
 constexpr int kMaxTileBlocks = 1536;
@@ -46,6 +46,11 @@ constexpr int kTile3X = 64, kTile3Y = 4, kTile3Z = 8;
 #endif
 constexpr int kFused3X = VFS_FUSED3_X, kFused3Y = VFS_FUSED3_Y, kFused3Z = VFS_FUSED3_Z;
 constexpr int kRow3X = kFused3X;
+// Row bits of the 3D solve: one word per kRow3X-anchor row (x part, y, z);
+// bit s (s < 6) is set if sample slice s has an active sample among the first
+// kRow3X / 2 anchors of the row, bit 6 + s among the second half.  With rows
+// that start on 128-byte lines, a half row of FP32 values is one line.
+using RowBits = uint16_t;
 static_assert(kTile3X % kFused3X == 0 && kFused3X >= 16 && kFused3Y % kTile3Y == 0 &&
                   kFused3Z % kTile3Z == 0 && kFused3X * kFused3Y <= 1024 &&
                   (kFused3X * kFused3Y) % 64 == 0,
@@ -221,6 +226,7 @@ struct vfs_ctx {
     float* a32 = nullptr;
     float* c32 = nullptr;
     float* dinv32 = nullptr;
+    float* ead32 = nullptr;   // 3D: a D^-1, the weighted preconditioner of the fused iteration
 
     // solver vectors (padded samples)
     double* x = nullptr;
@@ -264,7 +270,7 @@ struct vfs_ctx {
     int* ftile_flags = nullptr;
     int* ftile_list = nullptr;
     vfs::Tiles ftiles{nullptr, 0, 0, 0, 0};
-    uint8_t* rowbits = nullptr;
+    vfs::RowBits* rowbits = nullptr;
     // the (slice, row) items of the set row bits, built on the first FP64
     // brick-preconditioned solve after an assembly (launch_row_list)
     int* rowlist = nullptr;
@@ -360,10 +366,10 @@ struct RowList {
 };
 long long row_items(const Geo& g);
 int row_list_chunks(const Geo& g);
-void launch_row_list(const Geo& g, const uint8_t* rows, int* list, int* cnt, hipStream_t st);
+void launch_row_list(const Geo& g, const RowBits* rows, int* list, int* cnt, hipStream_t st);
 int schwarz_brick(int dim, int overlap);
 void launch_schwarz(const Geo& g, int overlap, const double* r, const double* a, const double* c,
-                    const double* dinv, const double* K, const uint8_t* rows, double* z,
+                    const double* dinv, const double* K, const RowBits* rows, double* z,
                     const int* done, hipStream_t st);
 int pcg_blocks(const Geo& g);
 void launch_pcg_dot(const Geo& g, const RowList& rl, const double* u, const double* v,
@@ -386,6 +392,7 @@ void launch_unpack_active(const Geo& g, const int shp[3], const double* a, uint8
 void launch_check(const double* v, long long n, int positive, int* flag, hipStream_t s);
 void launch_zero_box_faces(const Geo& g, double* faces, hipStream_t s);
 void launch_to_f32(const double* src, float* dst, long long n, hipStream_t s);
+void launch_mul_to_f32(const double* u, const double* v, float* dst, long long n, hipStream_t s);
 void launch_mask(double* dst, const double* src, const double* a, long long n, hipStream_t s);
 void launch_sub_mask(double* dst, const double* x, const double* y, const double* a, long long n,
                      hipStream_t s);
@@ -411,15 +418,15 @@ int dir3d_grid(int count, int word);
 // from the tile flags), skipping the rows of rowbits without an active sample
 int fused3d_grid(int count);
 void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v,
-                    const float* dinv, const float* a, const float* c, const float* K,
-                    const uint8_t* rows, const RedArgs& ra, hipStream_t s);
+                    const float* ead, const float* a, const float* c, const float* K,
+                    const RowBits* rows, const RedArgs& ra, hipStream_t s);
 void fused_tile_dims(const Geo& g, int& ntx, int& nty, int& ntz);
 void launch_fused_tiles(const Geo& g, const int* tile_flags, int* flags, int* list, int* count,
                         hipStream_t s);
 // plane split of the fused work tiles (their Tiles::split)
 int fused_split(int count, int capacity);
 long long row_bytes(const Geo& g);
-void launch_row_bits(const Geo& g, const double* a, uint8_t* rows, hipStream_t s);
+void launch_row_bits(const Geo& g, const double* a, RowBits* rows, hipStream_t s);
 // anchor positions of one tile of the 3D kernels and of the fused 2D kernel
 int tile3d_anchors();
 // plane split of a 3D tile list (Tiles::split)
