@@ -72,7 +72,10 @@ extern "C" {
 /* arithmetic of the solve */
 #define VFS_FP64   0   /* FP64 vectors, coefficients, apply and reductions */
 #define VFS_MIXED  1   /* FP32 apply/vectors, FP64 reductions, FP64 residual
-                          and iterative-refinement outer steps */
+                          and iterative-refinement outer steps; in 3D the six
+                          FP32 sample slices of one vector must stay under
+                          4 GiB (grids up to about 550^3), else the solve
+                          returns VFS_EINVAL */
 
 /* sample types, in sample order (index of a block of a sample-order vector);
  * the 3D-only types shift the 2D tau_xy to slot 3 */

@@ -550,7 +550,19 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
 #ifndef VFS_FUSED3_FOLD
 #define VFS_FUSED3_FOLD 1
 #endif
-constexpr int FTX = kFused3X, FTY = kFused3Y, FKZ = kFused3Z, FNT = FTX * FTY;
+// The kernel runs with G = 1 or 2 threads per anchor.  With G = 2, slice
+// group 0 (p, tau_xx, tau_yy) and slice group 1 (tau_xy, tau_xz, tau_yz) are
+// waves 0-3 and 4-7 of the workgroup; each thread keeps the prefetched plane
+// of three slices only, so the kernel fits in 128 VGPRs and 16 waves run per
+// CU instead of 8.  The bytes in flight per CU stay the same (two workgroups
+// of one tile each), so G = 2 pays off where a workgroup has few planes to
+// march (short tile lists split in z), and G = 1 where the sweep is long.
+constexpr int FTX = kFused3X, FTY = kFused3Y, FKZ = kFused3Z;
+constexpr int FNA = FTX * FTY;
+// a tile list split into at least this many z parts runs with G = 2
+#ifndef VFS_FUSED3_PAIR_SPLIT
+#define VFS_FUSED3_PAIR_SPLIT 2
+#endif
 constexpr int FHX = FTX + 2, FHY = FTY + 2, FFX = FTX + 1, FFY = FTY + 1;
 
 // the last x tile is folded into the one before it (nx a multiple of FTX)
@@ -570,6 +582,30 @@ __device__ __forceinline__ unsigned half_bits(unsigned rb, int lane) {
     return (lane >= kRow3X / 2 ? rb >> 6 : rb) & 63u;
 }
 
+// Byte offset of anchor (i, j, k) within a sample slice of FP32 values, or 0
+// (the slice's zero pad) when ok is false.  The fused iteration adds the
+// slice's offset s * NP * 4 and addresses every array from its base, so all
+// six slices must lie within 4 GiB (checked before its launch); the mask
+// replaces a select and the empty asm hides the value from the optimizer, so
+// that every access keeps the scalar-base form (array base in SGPRs, 32-bit
+// offset in one VGPR).
+__device__ __forceinline__ unsigned boff3(const Geo& g, int i, int j, int k, bool ok) {
+    const unsigned e = (unsigned)kFront +
+                       ((unsigned)(k + 1) * (unsigned)g.PY + (unsigned)(j + 1)) * (unsigned)g.PX +
+                       (unsigned)i;
+    unsigned b = (e * 4u) & (0u - (unsigned)ok);
+    asm("" : "+v"(b));
+    return b;
+}
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* __restrict__ base, unsigned boff) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* __restrict__ base, unsigned boff, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
 // Anchors of fused work item u: x from i0, y from j0, planes [k0, kend).
 __device__ __forceinline__ void fused_origin(const Tiles& t, const Geo& g, int u, int& tx, int& j0,
                                              int& k0, int& kend) {
@@ -583,26 +619,27 @@ __device__ __forceinline__ void fused_origin(const Tiles& t, const Geo& g, int u
     kend = min(k0 + kz, g.nz + 1);
 }
 
-template <typename T>
+template <typename T, int NS>
 struct FusedOwn {
-    T r[6], q[6], P[6], e[6], a[6], x[6];   // P = a p, e = a D^-1
-    T c[5];       // compliance coefficients of the own anchor one plane below
-    unsigned m;   // row bits of the plane
+    T r[NS], q[NS], P[NS], e[NS], a[NS], x[NS];   // P = a p, e = a D^-1
+    T c[NS];      // compliance coefficients of the own anchor one plane below
+    unsigned m;   // row bits of the plane (this thread's slices)
 };
-template <typename T>
+template <typename T, int NS>
 struct FusedHalo {
-    T r[6], q[6], P[6], e[6];
+    T r[NS], q[NS], P[NS], e[NS];
     T x3, x4, c3, c4, a3, a4;   // x, c and a of tau_xy, tau_xz in the folded column i = nx
     unsigned m;
 };
 
-template <typename T, bool INIT>
-__global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
-                                                 const T* __restrict__ ead,
-                                                 const T* __restrict__ a,
-                                                 const T* __restrict__ c,
-                                                 const T* __restrict__ K,
-                                                 const RowBits* __restrict__ rows, RedArgs ra) {
+template <typename T, bool INIT, int G>
+__global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
+                                                    const T* __restrict__ ead,
+                                                    const T* __restrict__ a,
+                                                    const T* __restrict__ c,
+                                                    const T* __restrict__ K,
+                                                    const RowBits* __restrict__ rows, RedArgs ra) {
+    constexpr int FNS = 6 / G, FNT = G * FNA;   // slices and threads per anchor / workgroup
     Scalars* sc = ra.sc;
     const int kidx = ra.kidx;
     const int pin = (kidx + 1) & 1, pout = kidx & 1;   // launch k reads (k-1)&1, writes k&1
@@ -615,7 +652,7 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
     T* __restrict__ x = static_cast<T*>(v.x);
 
     // totals of the previous launch -> stop decision, alpha_{k-1}, beta_k
-    PartialLoads<5, FNT, 2> pl;
+    PartialLoads<5, FNT, 2 / G> pl;
     if (!INIT) pl.load(ra.part_in, ra.nb_in);
     if (!INIT && sc->done) return;
     T alpha = T(0), beta = T(0);
@@ -663,19 +700,29 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
     // x tiles xt - 1, xt, xt + 1 (read once per item, so that no plane waits
     // on a global load before it can issue its own)
     __shared__ RowBits sRB[FKZ + 2][FHY][3];
-    const long long NP = g.NP;
+    // p, a, z and D^-1 of a thread's own samples, from the commit of a plane to
+    // the outputs of that plane: registers with G = 1, per-thread LDS slots by
+    // plane parity with G = 2 (128 VGPRs leave no room for them)
+    constexpr int NOWN = G == 2 ? FNT : 1;
+    __shared__ T sOwn[2][4][FNS][NOWN];
+    const unsigned NPB = (unsigned)g.NP * 4u;   // bytes of a slice (6 slices < 4 GiB)
     const int tid = threadIdx.x;
-    const int tx = tid % FTX, ty = tid / FTX;
-    const bool hrole = tid < 2 * FHX + 2 * FTY;
+    // slice group (uniform per wave) and anchor of the plane
+    const int grp = G == 1 ? 0 : __builtin_amdgcn_readfirstlane(tid / FNA);
+    const int ot = G == 1 ? tid : tid % FNA;
+    const int s0 = grp * FNS;                    // first slice of this thread
+    const unsigned gmask = ((1u << FNS) - 1u) << s0;
+    const int tx = ot % FTX, ty = ot / FTX;
+    const bool hrole = ot < 2 * FHX + 2 * FTY;
     int hli = 0, hlj = 0;
-    if (tid < FHX) {
-        hli = tid;
+    if (ot < FHX) {
+        hli = ot;
         hlj = 0;
-    } else if (tid < 2 * FHX) {
-        hli = tid - FHX;
+    } else if (ot < 2 * FHX) {
+        hli = ot - FHX;
         hlj = FHY - 1;
     } else if (hrole) {
-        const int e = tid - 2 * FHX;
+        const int e = ot - 2 * FHX;
         hlj = 1 + (e >> 1);
         hli = (e & 1) ? FHX - 1 : 0;
     }
@@ -685,8 +732,10 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
     const int hlane = hdt < 0 ? FTX - 1 : (hdt > 0 ? 0 : hli - 1);
     const int rntx = (g.nx + kRow3X) / kRow3X;   // x parts of the row bits
     const bool fold = fused_fold(g.nx);
-    // right x-halo threads of the own rows: owners of the folded column
-    const bool xrole = fold && hrole && tid >= 2 * FHX && hli == FHX - 1;
+    // right x-halo threads of the own rows that hold tau_xy, tau_xz: owners
+    // of the folded column (its two slices are q = qx, qx + 1 of the thread)
+    const bool xrole = fold && s0 + FNS > 4 && hrole && ot >= 2 * FHX && hli == FHX - 1;
+    constexpr int qx = FNS - 3;
     constexpr int NF = (FFX * FFY + FNT - 1) / FNT;
     double rz_n = 0.0, rr_n = 0.0, pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
     const TileRange trg = tile_range(ft.items());
@@ -705,100 +754,113 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                 (RowBits)row_bits_at(g, rows, rntx, xt + part - 1, j0 - 1 + rw, k0 - 1 + pl);
         }
 
-        auto fetch = [&](int kk, FusedOwn<T>& o, FusedHalo<T>& h) {
+        auto fetch = [&](int kk, FusedOwn<T, FNS>& o, FusedHalo<T, FNS>& h) {
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
             const int pl = kk - k0 + 1;
-            o.m = io <= g.nx + 1 ? half_bits(sRB[pl][ty + 1][1], tx) : 0u;
-            const long long oo = o.m ? g.idx(io, jo, kk) : 0;
-            h.m = (hrole && ih <= g.nx + 1) ? half_bits(sRB[pl][hlj][hdt + 1], hlane) : 0u;
-            const long long oh = h.m ? g.idx(ih, jh, kk) : 0;
+            o.m = io <= g.nx + 1 ? half_bits(sRB[pl][ty + 1][1], tx) & gmask : 0u;
+            const unsigned oo = boff3(g, io, jo, kk, o.m != 0u);
+            h.m = (hrole && ih <= g.nx + 1) ? half_bits(sRB[pl][hlj][hdt + 1], hlane) & gmask : 0u;
+            const unsigned oh = boff3(g, ih, jh, kk, h.m != 0u);
             // c of the own anchor at plane kk - 1 (the plane whose outputs are
-            // formed while this one is being committed)
+            // formed while this one is being committed); p has none
             const bool ownb = io <= g.nx && jo <= g.ny && kk - 1 >= k0 && kk - 1 < kend;
-            const unsigned mb = ownb ? half_bits(sRB[pl - 1][ty + 1][1], tx) : 0u;
-            const long long ob = mb ? g.idx(io, jo, kk - 1) : 0;
+            const unsigned mb = ownb ? half_bits(sRB[pl - 1][ty + 1][1], tx) & gmask & ~1u : 0u;
+            const unsigned ob = boff3(g, io, jo, kk - 1, mb != 0u);
 #pragma unroll
-            for (int s = 0; s < 5; ++s) o.c[s] = ((mb >> (s + 1)) & 1u) ? c[(s + 1) * NP + ob] : T(0);
+            for (int q = 0; q < FNS; ++q) {
+                const int s = s0 + q;
+                o.c[q] = ((mb >> s) & 1u) ? ld_at(c, ob + (unsigned)s * NPB) : T(0);
+            }
             const bool hx = xown && kk >= k0 && kk < kend;
             const bool h3 = hx && ((h.m >> 3) & 1u), h4 = hx && ((h.m >> 4) & 1u);
-            h.x3 = (h3 && !INIT) ? x[3 * NP + oh] : T(0);
-            h.x4 = (h4 && !INIT) ? x[4 * NP + oh] : T(0);
-            h.c3 = h3 ? c[3 * NP + oh] : T(0);
-            h.c4 = h4 ? c[4 * NP + oh] : T(0);
-            h.a3 = h3 ? a[3 * NP + oh] : T(0);
-            h.a4 = h4 ? a[4 * NP + oh] : T(0);
+            h.x3 = (h3 && !INIT) ? ld_at(x, oh + 3u * NPB) : T(0);
+            h.x4 = (h4 && !INIT) ? ld_at(x, oh + 4u * NPB) : T(0);
+            h.c3 = h3 ? ld_at(c, oh + 3u * NPB) : T(0);
+            h.c4 = h4 ? ld_at(c, oh + 4u * NPB) : T(0);
+            h.a3 = h3 ? ld_at(a, oh + 3u * NPB) : T(0);
+            h.a4 = h4 ? ld_at(a, oh + 4u * NPB) : T(0);
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const long long so = oo + s * NP, sh = oh + s * NP;
+            for (int q = 0; q < FNS; ++q) {
+                const int s = s0 + q;
+                const unsigned sb = (unsigned)s * NPB;   // slice offset in bytes (uniform)
                 const bool lo = (o.m >> s) & 1u, lh = (h.m >> s) & 1u;
-                o.r[s] = lo ? r_in[so] : T(0);
-                o.e[s] = lo ? ead[so] : T(0);
-                o.a[s] = lo ? a[so] : T(0);
-                o.q[s] = (lo && !INIT) ? q_in[so] : T(0);
-                o.P[s] = (lo && !INIT) ? p_in[so] : T(0);
-                o.x[s] = (lo && own && !INIT) ? x[so] : T(0);
-                h.r[s] = lh ? r_in[sh] : T(0);
-                h.e[s] = lh ? ead[sh] : T(0);
-                h.q[s] = (lh && !INIT) ? q_in[sh] : T(0);
-                h.P[s] = (lh && !INIT) ? p_in[sh] : T(0);
+                o.r[q] = lo ? ld_at(r_in, oo + sb) : T(0);
+                o.e[q] = lo ? ld_at(ead, oo + sb) : T(0);
+                o.a[q] = lo ? ld_at(a, oo + sb) : T(0);
+                o.q[q] = (lo && !INIT) ? ld_at(q_in, oo + sb) : T(0);
+                o.P[q] = (lo && !INIT) ? ld_at(p_in, oo + sb) : T(0);
+                o.x[q] = (lo && own && !INIT) ? ld_at(x, oo + sb) : T(0);
+                h.r[q] = lh ? ld_at(r_in, oh + sb) : T(0);
+                h.e[q] = lh ? ld_at(ead, oh + sb) : T(0);
+                h.q[q] = (lh && !INIT) ? ld_at(q_in, oh + sb) : T(0);
+                h.P[q] = (lh && !INIT) ? ld_at(p_in, oh + sb) : T(0);
             }
         };
-        // r_k, z_k, p_k of plane kk into the ring slot; own anchors also store
-        // r_k, x_k, p_k and add to r.z, r.r; own p, a, z, D^-1 and row bits out
-        auto commit = [&](int kk, const FusedOwn<T>& o, const FusedHalo<T>& h, T (&vo)[6],
-                          T (&ao)[6], T (&zo)[6], T (&dq)[6], unsigned& mo, T (&cb)[5]) {
+        // r_k and a p_k of plane kk into the ring slot; own anchors also store
+        // r_k, x_k, P_k and add to r.z, r.r; own p, a, z, D^-1, c and row bits out
+        auto commit = [&](int kk, const FusedOwn<T, FNS>& o, const FusedHalo<T, FNS>& h,
+                          T (&vo)[FNS], T (&ao)[FNS], T (&zo)[FNS], T (&dq)[FNS], unsigned& mo,
+                          T (&cb)[FNS]) {
             const int sl = kk & 1;
 #pragma unroll
-            for (int s = 0; s < 5; ++s) cb[s] = o.c[s];
+            for (int q = 0; q < FNS; ++q) cb[q] = o.c[q];
             const bool own = io <= g.nx && jo <= g.ny && kk >= k0 && kk < kend;
-            const long long oo = own ? g.idx(io, jo, kk) : 0;
             mo = own ? o.m : 0u;
+            const unsigned oo = boff3(g, io, jo, kk, mo != 0u);
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const T rn = INIT ? o.r[s] : o.r[s] - alpha * o.q[s];
-                const T W = INIT ? o.e[s] * rn : o.e[s] * rn + beta * o.P[s];   // a p_k
-                const T ia = o.a[s] != T(0) ? T(1) / o.a[s] : T(0);
-                const T dd = o.e[s] * ia;   // D^-1
+            for (int q = 0; q < FNS; ++q) {
+                const int s = s0 + q;
+                const T rn = INIT ? o.r[q] : o.r[q] - alpha * o.q[q];
+                const T W = INIT ? o.e[q] * rn : o.e[q] * rn + beta * o.P[q];   // a p_k
+                const T ia = o.a[q] != T(0) ? T(1) / o.a[q] : T(0);
+                const T dd = o.e[q] * ia;   // D^-1
                 const T zn = dd * rn;
                 if ((mo >> s) & 1u) {
-                    const long long os = oo + s * NP;
+                    const unsigned sb = (unsigned)s * NPB;
                     if (!INIT) {
-                        r_out[os] = rn;
-                        x[os] = o.x[s] + alpha * (o.P[s] * ia);
+                        st_at(r_out, oo + sb, rn);
+                        st_at(x, oo + sb, o.x[q] + alpha * (o.P[q] * ia));
                     }
-                    p_out[os] = W;
+                    st_at(p_out, oo + sb, W);
                     rz_n += (double)rn * (double)zn;
                     rr_n += (double)rn * (double)rn;
                 }
-                vo[s] = W * ia;
-                ao[s] = o.a[s];
-                zo[s] = zn;
-                dq[s] = dd;
+                if constexpr (G == 1) {
+                    vo[q] = W * ia;
+                    ao[q] = o.a[q];
+                    zo[q] = zn;
+                    dq[q] = dd;
+                } else {
+                    sOwn[sl][0][q][tid] = W * ia;
+                    sOwn[sl][1][q][tid] = o.a[q];
+                    sOwn[sl][2][q][tid] = zn;
+                    sOwn[sl][3][q][tid] = dd;
+                }
                 sW[sl][s][ty + 1][tx + 1] = W;
             }
             if (hrole) {
 #pragma unroll
-                for (int s = 0; s < 6; ++s) {
-                    const T rn = INIT ? h.r[s] : h.r[s] - alpha * h.q[s];
-                    sW[sl][s][hlj][hli] = INIT ? h.e[s] * rn : h.e[s] * rn + beta * h.P[s];
+                for (int q = 0; q < FNS; ++q) {
+                    const T rn = INIT ? h.r[q] : h.r[q] - alpha * h.q[q];
+                    sW[sl][s0 + q][hlj][hli] = INIT ? h.e[q] * rn : h.e[q] * rn + beta * h.P[q];
                 }
             }
-            // the folded column: tau_xy (slice 3) and tau_xz (slice 4) at
-            // (nx, jh); what its outputs need later waits in this thread's
-            // LDS slots (registers are exhausted)
+            // the folded column: tau_xy (slice 3, q 0) and tau_xz (slice 4,
+            // q 1) at (nx, jh); what its outputs need later waits in this
+            // thread's LDS slots
             if (xown) {
                 const unsigned xm = (kk >= k0 && kk < kend) ? (h.m & 0x18u) : 0u;
                 sXM[sl][hlj - 1] = xm;
-                const long long oh = xm ? g.idx(ih, jh, kk) : 0;
+                const unsigned oh = boff3(g, ih, jh, kk, xm != 0u);
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     const int s = 3 + e;
                     if (!((xm >> s) & 1u)) continue;
-                    const T rn = INIT ? h.r[s] : h.r[s] - alpha * h.q[s];
-                    const T W = INIT ? h.e[s] * rn : h.e[s] * rn + beta * h.P[s];
+                    const T rn = INIT ? h.r[qx + e] : h.r[qx + e] - alpha * h.q[qx + e];
+                    const T W = INIT ? h.e[qx + e] * rn : h.e[qx + e] * rn + beta * h.P[qx + e];
                     const T as = e ? h.a4 : h.a3;
                     const T ia = as != T(0) ? T(1) / as : T(0);
-                    const T dd = h.e[s] * ia;
+                    const T dd = h.e[qx + e] * ia;
                     const T zn = dd * rn;
                     T* f = sXF[sl][hlj - 1][e];
                     f[0] = W * ia;
@@ -806,12 +868,12 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                     f[2] = zn;
                     f[3] = dd;
                     f[4] = e ? h.c4 : h.c3;
-                    const long long os = oh + s * NP;
+                    const unsigned sb = (unsigned)s * NPB;
                     if (!INIT) {
-                        r_out[os] = rn;
-                        x[os] = (e ? h.x4 : h.x3) + alpha * (h.P[s] * ia);
+                        st_at(r_out, oh + sb, rn);
+                        st_at(x, oh + sb, (e ? h.x4 : h.x3) + alpha * (h.P[qx + e] * ia));
                     }
-                    p_out[os] = W;
+                    st_at(p_out, oh + sb, W);
                     rz_n += (double)rn * (double)zn;
                     rr_n += (double)rn * (double)rn;
                 }
@@ -825,45 +887,50 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                 ku[m] = kv[m] = kw[m] = T(0);
                 if (e < FFX * FFY) {
                     const int iu = i0 + li, ju = j0 - 1 + lj;
-                    if (iu <= g.nx && ju >= 0 && ju < g.ny && kk >= 0 && kk < g.nz)
-                        ku[m] = K[g.idx(iu, ju, kk)];
+                    const bool bu = iu <= g.nx && ju >= 0 && ju < g.ny && kk >= 0 && kk < g.nz;
+                    const unsigned fu = boff3(g, iu, ju, kk, bu);
+                    if (bu) ku[m] = ld_at(K, fu);
                     const int iv = i0 - 1 + li, jv = j0 + lj;
-                    if (iv >= 0 && iv < g.nx && jv <= g.ny && kk >= 0 && kk < g.nz)
-                        kv[m] = K[NP + g.idx(iv, jv, kk)];
+                    const bool bv = iv >= 0 && iv < g.nx && jv <= g.ny && kk >= 0 && kk < g.nz;
+                    const unsigned fv = boff3(g, iv, jv, kk, bv);
+                    if (bv) kv[m] = ld_at(K, fv + NPB);
                     const int iw = i0 - 1 + li, jw = j0 - 1 + lj, kw2 = kk + 1;
-                    if (iw >= 0 && iw < g.nx && jw >= 0 && jw < g.ny && kw2 >= 0 && kw2 <= g.nz)
-                        kw[m] = K[2 * NP + g.idx(iw, jw, kw2)];
+                    const bool bw = iw >= 0 && iw < g.nx && jw >= 0 && jw < g.ny && kw2 >= 0 &&
+                                    kw2 <= g.nz;
+                    const unsigned fw = boff3(g, iw, jw, kw2, bw);
+                    if (bw) kw[m] = ld_at(K, fw + 2u * NPB);
                 }
             }
         };
         auto faces = [&](int kk, const T (&ku)[NF], const T (&kv)[NF], const T (&kw)[NF]) {
-            const int s0 = kk & 1, s1 = (kk + 1) & 1;
+            const int s0f = kk & 1, s1f = (kk + 1) & 1;
 #pragma unroll
             for (int m = 0; m < NF; ++m) {
                 const int e = tid + m * FNT;
                 if (e >= FFX * FFY) continue;
                 const int li = e % FFX, lj = e / FFX;
-                gU[s0][lj][li] = ku[m] * ((sW[s0][0][lj][li + 1] - sW[s0][0][lj][li]) +
-                                          (sW[s0][1][lj][li] - sW[s0][1][lj][li + 1]) +
-                                          (sW[s0][3][lj][li + 1] - sW[s0][3][lj + 1][li + 1]) +
-                                          (sW[s0][4][lj][li + 1] - sW[s1][4][lj][li + 1]));
-                gV[s0][lj][li] = kv[m] * ((sW[s0][0][lj + 1][li] - sW[s0][0][lj][li]) +
-                                          (sW[s0][2][lj][li] - sW[s0][2][lj + 1][li]) +
-                                          (sW[s0][3][lj + 1][li] - sW[s0][3][lj + 1][li + 1]) +
-                                          (sW[s0][5][lj + 1][li] - sW[s1][5][lj + 1][li]));
-                gW[s1][lj][li] = kw[m] * ((sW[s1][0][lj][li] - sW[s0][0][lj][li]) +
-                                          (sW[s1][1][lj][li] - sW[s0][1][lj][li]) +
-                                          (sW[s1][2][lj][li] - sW[s0][2][lj][li]) +
-                                          (sW[s1][4][lj][li] - sW[s1][4][lj][li + 1]) +
-                                          (sW[s1][5][lj][li] - sW[s1][5][lj + 1][li]));
+                gU[s0f][lj][li] = ku[m] * ((sW[s0f][0][lj][li + 1] - sW[s0f][0][lj][li]) +
+                                           (sW[s0f][1][lj][li] - sW[s0f][1][lj][li + 1]) +
+                                           (sW[s0f][3][lj][li + 1] - sW[s0f][3][lj + 1][li + 1]) +
+                                           (sW[s0f][4][lj][li + 1] - sW[s1f][4][lj][li + 1]));
+                gV[s0f][lj][li] = kv[m] * ((sW[s0f][0][lj + 1][li] - sW[s0f][0][lj][li]) +
+                                           (sW[s0f][2][lj][li] - sW[s0f][2][lj + 1][li]) +
+                                           (sW[s0f][3][lj + 1][li] - sW[s0f][3][lj + 1][li + 1]) +
+                                           (sW[s0f][5][lj + 1][li] - sW[s1f][5][lj + 1][li]));
+                gW[s1f][lj][li] = kw[m] * ((sW[s1f][0][lj][li] - sW[s0f][0][lj][li]) +
+                                           (sW[s1f][1][lj][li] - sW[s0f][1][lj][li]) +
+                                           (sW[s1f][2][lj][li] - sW[s0f][2][lj][li]) +
+                                           (sW[s1f][4][lj][li] - sW[s1f][4][lj][li + 1]) +
+                                           (sW[s1f][5][lj][li] - sW[s1f][5][lj + 1][li]));
             }
         };
 
-        T vcur[6], acur[6], zcur[6], dcur[6], vnext[6], anext[6], znext[6], dnext[6];
+        T vcur[FNS], acur[FNS], zcur[FNS], dcur[FNS], vnext[FNS], anext[FNS], znext[FNS],
+            dnext[FNS];
         unsigned mcur, mnext;
-        FusedOwn<T> Fo;
-        FusedHalo<T> Fh;
-        T Ku[NF], Kv[NF], Kw[NF], Cc[5];
+        FusedOwn<T, FNS> Fo;
+        FusedHalo<T, FNS> Fh;
+        T Ku[NF], Kv[NF], Kw[NF], Cc[FNS];
         __syncthreads();   // row bits of this item in LDS
         fetch(k0 - 1, Fo, Fh);
         fetchK(k0 - 1, Ku, Kv, Kw);
@@ -886,30 +953,48 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
             __syncthreads();
             if (mcur) {
                 const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;
-                const T gu0 = gU[sk][ty + 1][tx], gu1 = gU[sk][ty + 1][tx + 1];
-                const T gum = gU[sk][ty][tx], guz = gU[sp][ty + 1][tx];
-                const T gv0 = gV[sk][ty][tx + 1], gv1 = gV[sk][ty + 1][tx + 1];
-                const T gvm = gV[sk][ty][tx], gvz = gV[sp][ty][tx + 1];
-                const T gw0 = gW[sk][ty + 1][tx + 1], gw1 = gW[sn][ty + 1][tx + 1];
-                const T gwx = gW[sk][ty + 1][tx], gwy = gW[sk][ty][tx + 1];
-                const long long o = g.idx(io, jo, k);
-                const T c1 = Cc[0], c2 = Cc[1];
-                const T cross = T(0.5) * fmin(c1, c2);
-                T y[6];
-                y[0] = acur[0] * ((gu0 - gu1) + (gv0 - gv1) + (gw0 - gw1));
-                y[1] = acur[1] * ((gu1 - gu0) + (gw0 - gw1)) + c1 * vcur[1] + cross * vcur[2];
-                y[2] = acur[2] * ((gv1 - gv0) + (gw0 - gw1)) + c2 * vcur[2] + cross * vcur[1];
-                y[3] = acur[3] * ((gu0 - gum) + (gv0 - gvm)) + Cc[2] * vcur[3];
-                y[4] = acur[4] * ((gu0 - guz) + (gw0 - gwx)) + Cc[3] * vcur[4];
-                y[5] = acur[5] * ((gv0 - gvz) + (gw0 - gwy)) + Cc[4] * vcur[5];
+                if constexpr (G == 2) {
 #pragma unroll
-                for (int s = 0; s < 6; ++s) {
+                    for (int q = 0; q < FNS; ++q) {
+                        vcur[q] = sOwn[sk][0][q][tid];
+                        acur[q] = sOwn[sk][1][q][tid];
+                    }
+                }
+                const T gu0 = gU[sk][ty + 1][tx], gv0 = gV[sk][ty][tx + 1];
+                const T gw0 = gW[sk][ty + 1][tx + 1];
+                T y[FNS];
+                if (G == 1 || grp == 0) {   // p, tau_xx, tau_yy: q = 0, 1, 2
+                    const T gu1 = gU[sk][ty + 1][tx + 1], gv1 = gV[sk][ty + 1][tx + 1];
+                    const T gw1 = gW[sn][ty + 1][tx + 1];
+                    const T c1 = Cc[1], c2 = Cc[2];
+                    const T cross = T(0.5) * fmin(c1, c2);
+                    y[0] = acur[0] * ((gu0 - gu1) + (gv0 - gv1) + (gw0 - gw1));
+                    y[1] = acur[1] * ((gu1 - gu0) + (gw0 - gw1)) + c1 * vcur[1] + cross * vcur[2];
+                    y[2] = acur[2] * ((gv1 - gv0) + (gw0 - gw1)) + c2 * vcur[2] + cross * vcur[1];
+                }
+                if (G == 1 || grp == 1) {   // tau_xy, tau_xz, tau_yz: q = b, b + 1, b + 2
+                    constexpr int b = FNS - 3;
+                    const T gum = gU[sk][ty][tx], guz = gU[sp][ty + 1][tx];
+                    const T gvm = gV[sk][ty][tx], gvz = gV[sp][ty][tx + 1];
+                    const T gwx = gW[sk][ty + 1][tx], gwy = gW[sk][ty][tx + 1];
+                    y[b] = acur[b] * ((gu0 - gum) + (gv0 - gvm)) + Cc[b] * vcur[b];
+                    y[b + 1] = acur[b + 1] * ((gu0 - guz) + (gw0 - gwx)) + Cc[b + 1] * vcur[b + 1];
+                    y[b + 2] = acur[b + 2] * ((gv0 - gvz) + (gw0 - gwy)) + Cc[b + 2] * vcur[b + 2];
+                }
+                const unsigned o = boff3(g, io, jo, k, true);
+#pragma unroll
+                for (int q = 0; q < FNS; ++q) {
+                    const int s = s0 + q;
                     if (!((mcur >> s) & 1u)) continue;
-                    q_out[s * NP + o] = y[s];
-                    const double yd = y[s];
-                    pq_n += (double)vcur[s] * yd;
-                    qz_n += (double)zcur[s] * yd;
-                    qdq_n += (double)dcur[s] * yd * yd;
+                    st_at(q_out, o + (unsigned)s * NPB, y[q]);
+                    const double yd = y[q];
+                    pq_n += (double)vcur[q] * yd;
+                    if constexpr (G == 2) {
+                        zcur[q] = sOwn[sk][2][q][tid];
+                        dcur[q] = sOwn[sk][3][q][tid];
+                    }
+                    qz_n += (double)zcur[q] * yd;
+                    qdq_n += (double)dcur[q] * yd * yd;
                 }
             }
             const unsigned xmc = xown ? sXM[k & 1][hlj - 1] : 0u;
@@ -919,25 +1004,27 @@ __global__ __launch_bounds__(FNT) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                 const T guz = gU[sp][hlj][FTX];
                 const T gvm = gV[sk][hlj - 1][FTX], gwx = gW[sk][hlj][FTX];
                 const T fl[2] = {(gu0 - gum) - gvm, (gu0 - guz) - gwx};
-                const long long o = g.idx(ih, jh, k);
+                const unsigned o = boff3(g, ih, jh, k, true);
 #pragma unroll
                 for (int e = 0; e < 2; ++e) {
                     if (!((xmc >> (3 + e)) & 1u)) continue;
                     const T* f = sXF[sk][hlj - 1][e];
-                    const T y = f[1] * fl[e] + f[4] * f[0];
-                    q_out[(3 + e) * NP + o] = y;
-                    const double yd = y;
+                    const T yv = f[1] * fl[e] + f[4] * f[0];
+                    st_at(q_out, o + (unsigned)(3 + e) * NPB, yv);
+                    const double yd = yv;
                     pq_n += (double)f[0] * yd;
                     qz_n += (double)f[2] * yd;
                     qdq_n += (double)f[3] * yd * yd;
                 }
             }
+            if constexpr (G == 1) {
 #pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                vcur[s] = vnext[s];
-                acur[s] = anext[s];
-                zcur[s] = znext[s];
-                dcur[s] = dnext[s];
+                for (int q = 0; q < FNS; ++q) {
+                    vcur[q] = vnext[q];
+                    acur[q] = anext[q];
+                    zcur[q] = znext[q];
+                    dcur[q] = dnext[q];
+                }
             }
             mcur = mnext;
         }
@@ -1208,11 +1295,14 @@ int fused3d_grid(int count) {
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     int& c = cache[dev & 15];
     if (c == 0) {
-        int nb = 0, ncu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused3d<float, false>, FNT, 0) !=
-                hipSuccess ||
-            nb < 1)
-            nb = 1;
+        // the smaller residency of the two shapes (both hold two workgroups per CU)
+        int nb = 0, nb1 = 0, ncu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused3d<float, false, 2>,
+                                                         2 * FNA, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, k_fused3d<float, false, 1>, FNA,
+                                                         0) != hipSuccess)
+            nb = nb1 = 1;
+        nb = std::max(1, std::min(nb, nb1));
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             ncu < 1)
             ncu = 1;
@@ -1226,12 +1316,21 @@ void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v
                     const RowBits* rows, const RedArgs& ra, hipStream_t s) {
     if (ft.count <= 0) return;
     const dim3 gs(fused3d_grid(ft.items()));
-    if (init)
-        hipLaunchKernelGGL((k_fused3d<float, true>), gs, dim3(FNT), 0, s, g, ft, v, ead, a, c, K,
-                           rows, ra);
-    else
-        hipLaunchKernelGGL((k_fused3d<float, false>), gs, dim3(FNT), 0, s, g, ft, v, ead, a, c, K,
-                           rows, ra);
+    if (ft.split >= VFS_FUSED3_PAIR_SPLIT) {
+        if (init)
+            hipLaunchKernelGGL((k_fused3d<float, true, 2>), gs, dim3(2 * FNA), 0, s, g, ft, v,
+                               ead, a, c, K, rows, ra);
+        else
+            hipLaunchKernelGGL((k_fused3d<float, false, 2>), gs, dim3(2 * FNA), 0, s, g, ft, v,
+                               ead, a, c, K, rows, ra);
+    } else {
+        if (init)
+            hipLaunchKernelGGL((k_fused3d<float, true, 1>), gs, dim3(FNA), 0, s, g, ft, v, ead,
+                               a, c, K, rows, ra);
+        else
+            hipLaunchKernelGGL((k_fused3d<float, false, 1>), gs, dim3(FNA), 0, s, g, ft, v, ead,
+                               a, c, K, rows, ra);
+    }
 }
 
 template <typename T>

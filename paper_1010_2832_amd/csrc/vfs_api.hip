@@ -225,6 +225,10 @@ int run_chunks_fused(vfs_ctx* ctx, bool set_bb, Scalars* out) {
 // 3D counterpart of run_chunks_fused (k_fused3d over the active tiles).
 int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     const Geo& g = ctx->g;
+    // the kernel addresses the six FP32 slices of a vector with 32-bit byte offsets
+    if ((long long)g.nsamp() * g.NP * 4 >= (1LL << 32))
+        return fail(ctx, VFS_EINVAL,
+                    "grid too large for the mixed-precision 3D solve (a FP32 vector over 4 GiB)");
     hipStream_t s = ctx->stream;
     const int nb = fused3d_grid(ctx->ftiles.items());
     double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)kMaxTileBlocks + 32};
