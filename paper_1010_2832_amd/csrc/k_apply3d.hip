@@ -534,11 +534,16 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
 // row of one sample slice whose row bit is clear is neither loaded nor
 // stored: its values are known to be 0.
 //
-// The direction is kept weighted, P = a p (a = W_L), and the preconditioner
-// as e = a D^-1 (ad): the faces need a p_k = e r_k + beta P_{k-1} at every
-// position of the tile and its halo, which takes r, q, P and e (four loads
-// instead of five); the own anchors also read a and form p = P / a and
-// D^-1 = e / a for the update, the partials and the compliance term.
+// The faces need a p_k at every position of the tile and its halo.  The
+// direction is kept weighted, P = a p (a = W_L), and so are the residual and
+// A p, R = e r and Q = e q with e = a D^-1 (ead): then
+// a p_k = e (r_{k-1} - alpha q_{k-1}) + beta P_{k-1} = R_{k-1} - alpha Q_{k-1}
+// + beta P_{k-1} takes three loads per halo position (R, Q and P, where the
+// unweighted vectors took r, q, p, D^-1 and a).  The own anchors also read e
+// and a, and form r = R / e, z = D^-1 r = R / a, p = P / a and D^-1 = e / a
+// for the partials, the update of x and the compliance term; their A p is
+// stored as Q = (D^-1 a) A p.  The launch that starts a solve reads the plain
+// residual from the second r buffer and writes R_0 = e r_0 to the first.
 //
 // When nx is a multiple of FTX the anchors i = 0..nx need one x tile more than
 // nx / FTX, and that tile holds only the column i = nx, where only tau_xy and
@@ -643,7 +648,7 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
     Scalars* sc = ra.sc;
     const int kidx = ra.kidx;
     const int pin = (kidx + 1) & 1, pout = kidx & 1;   // launch k reads (k-1)&1, writes k&1
-    const T* __restrict__ r_in = static_cast<const T*>(v.r[INIT ? 0 : pin]);
+    const T* __restrict__ r_in = static_cast<const T*>(v.r[INIT ? 1 : pin]);
     const T* __restrict__ q_in = static_cast<const T*>(v.q[pin]);
     const T* __restrict__ p_in = static_cast<const T*>(v.p[pin]);
     T* __restrict__ r_out = static_cast<T*>(v.r[pout]);
@@ -791,13 +796,15 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                 o.P[q] = (lo && !INIT) ? ld_at(p_in, oo + sb) : T(0);
                 o.x[q] = (lo && own && !INIT) ? ld_at(x, oo + sb) : T(0);
                 h.r[q] = lh ? ld_at(r_in, oh + sb) : T(0);
-                h.e[q] = lh ? ld_at(ead, oh + sb) : T(0);
+                // the halo needs e only to weight the plain residual of the
+                // first launch, and for the own samples of the folded column
+                h.e[q] = (lh && (INIT || (hx && (s == 3 || s == 4)))) ? ld_at(ead, oh + sb) : T(0);
                 h.q[q] = (lh && !INIT) ? ld_at(q_in, oh + sb) : T(0);
                 h.P[q] = (lh && !INIT) ? ld_at(p_in, oh + sb) : T(0);
             }
         };
-        // r_k and a p_k of plane kk into the ring slot; own anchors also store
-        // r_k, x_k, P_k and add to r.z, r.r; own p, a, z, D^-1, c and row bits out
+        // a p_k of plane kk into the ring slot; own anchors also store R_k,
+        // x_k, P_k and add to r.z, r.r; own p, a, z, D^-1, c and row bits out
         auto commit = [&](int kk, const FusedOwn<T, FNS>& o, const FusedHalo<T, FNS>& h,
                           T (&vo)[FNS], T (&ao)[FNS], T (&zo)[FNS], T (&dq)[FNS], unsigned& mo,
                           T (&cb)[FNS]) {
@@ -810,17 +817,17 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
 #pragma unroll
             for (int q = 0; q < FNS; ++q) {
                 const int s = s0 + q;
-                const T rn = INIT ? o.r[q] : o.r[q] - alpha * o.q[q];
-                const T W = INIT ? o.e[q] * rn : o.e[q] * rn + beta * o.P[q];   // a p_k
+                const T Rn = INIT ? o.e[q] * o.r[q] : o.r[q] - alpha * o.q[q];   // e r_k
+                const T W = INIT ? Rn : Rn + beta * o.P[q];                         // a p_k
                 const T ia = o.a[q] != T(0) ? T(1) / o.a[q] : T(0);
-                const T dd = o.e[q] * ia;   // D^-1
-                const T zn = dd * rn;
+                const T ie = o.e[q] != T(0) ? __builtin_amdgcn_rcpf(o.e[q]) : T(0);
+                const T rn = INIT ? o.r[q] : Rn * ie;   // r_k (for the partials only)
+                const T dd = o.e[q] * ia;               // D^-1
+                const T zn = Rn * ia;                   // z_k = D^-1 r_k
                 if ((mo >> s) & 1u) {
                     const unsigned sb = (unsigned)s * NPB;
-                    if (!INIT) {
-                        st_at(r_out, oo + sb, rn);
-                        st_at(x, oo + sb, o.x[q] + alpha * (o.P[q] * ia));
-                    }
+                    st_at(r_out, oo + sb, Rn);
+                    if (!INIT) st_at(x, oo + sb, o.x[q] + alpha * (o.P[q] * ia));
                     st_at(p_out, oo + sb, W);
                     rz_n += (double)rn * (double)zn;
                     rr_n += (double)rn * (double)rn;
@@ -841,8 +848,8 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
             if (hrole) {
 #pragma unroll
                 for (int q = 0; q < FNS; ++q) {
-                    const T rn = INIT ? h.r[q] : h.r[q] - alpha * h.q[q];
-                    sW[sl][s0 + q][hlj][hli] = INIT ? h.e[q] * rn : h.e[q] * rn + beta * h.P[q];
+                    const T Rn = INIT ? h.e[q] * h.r[q] : h.r[q] - alpha * h.q[q];
+                    sW[sl][s0 + q][hlj][hli] = INIT ? Rn : Rn + beta * h.P[q];
                 }
             }
             // the folded column: tau_xy (slice 3, q 0) and tau_xz (slice 4,
@@ -856,12 +863,15 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                 for (int e = 0; e < 2; ++e) {
                     const int s = 3 + e;
                     if (!((xm >> s) & 1u)) continue;
-                    const T rn = INIT ? h.r[qx + e] : h.r[qx + e] - alpha * h.q[qx + e];
-                    const T W = INIT ? h.e[qx + e] * rn : h.e[qx + e] * rn + beta * h.P[qx + e];
+                    const T es = h.e[qx + e];
+                    const T Rn = INIT ? es * h.r[qx + e] : h.r[qx + e] - alpha * h.q[qx + e];
+                    const T W = INIT ? Rn : Rn + beta * h.P[qx + e];
                     const T as = e ? h.a4 : h.a3;
                     const T ia = as != T(0) ? T(1) / as : T(0);
-                    const T dd = h.e[qx + e] * ia;
-                    const T zn = dd * rn;
+                    const T ie = es != T(0) ? __builtin_amdgcn_rcpf(es) : T(0);
+                    const T rn = INIT ? h.r[qx + e] : Rn * ie;
+                    const T dd = es * ia;
+                    const T zn = Rn * ia;
                     T* f = sXF[sl][hlj - 1][e];
                     f[0] = W * ia;
                     f[1] = as;
@@ -869,10 +879,8 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                     f[3] = dd;
                     f[4] = e ? h.c4 : h.c3;
                     const unsigned sb = (unsigned)s * NPB;
-                    if (!INIT) {
-                        st_at(r_out, oh + sb, rn);
-                        st_at(x, oh + sb, (e ? h.x4 : h.x3) + alpha * (h.P[qx + e] * ia));
-                    }
+                    st_at(r_out, oh + sb, Rn);
+                    if (!INIT) st_at(x, oh + sb, (e ? h.x4 : h.x3) + alpha * (h.P[qx + e] * ia));
                     st_at(p_out, oh + sb, W);
                     rz_n += (double)rn * (double)zn;
                     rr_n += (double)rn * (double)rn;
@@ -986,13 +994,13 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                 for (int q = 0; q < FNS; ++q) {
                     const int s = s0 + q;
                     if (!((mcur >> s) & 1u)) continue;
-                    st_at(q_out, o + (unsigned)s * NPB, y[q]);
-                    const double yd = y[q];
-                    pq_n += (double)vcur[q] * yd;
                     if constexpr (G == 2) {
                         zcur[q] = sOwn[sk][2][q][tid];
                         dcur[q] = sOwn[sk][3][q][tid];
                     }
+                    st_at(q_out, o + (unsigned)s * NPB, (dcur[q] * acur[q]) * y[q]);   // e q
+                    const double yd = y[q];
+                    pq_n += (double)vcur[q] * yd;
                     qz_n += (double)zcur[q] * yd;
                     qdq_n += (double)dcur[q] * yd * yd;
                 }
@@ -1010,7 +1018,7 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                     if (!((xmc >> (3 + e)) & 1u)) continue;
                     const T* f = sXF[sk][hlj - 1][e];
                     const T yv = f[1] * fl[e] + f[4] * f[0];
-                    st_at(q_out, o + (unsigned)(3 + e) * NPB, yv);
+                    st_at(q_out, o + (unsigned)(3 + e) * NPB, (f[3] * f[1]) * yv);
                     const double yd = yv;
                     pq_n += (double)f[0] * yd;
                     qz_n += (double)f[2] * yd;

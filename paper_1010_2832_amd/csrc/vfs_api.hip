@@ -232,7 +232,8 @@ int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     hipStream_t s = ctx->stream;
     const int nb = fused3d_grid(ctx->ftiles.items());
     double* part[2] = {ctx->fpart, ctx->fpart + 5 * (long long)kMaxTileBlocks + 32};
-    const FusedVecs fv{ctx->x32, {ctx->r32, ctx->z32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
+    // the first launch reads the plain residual from r32 and writes e r to z32
+    const FusedVecs fv{ctx->x32, {ctx->z32, ctx->r32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
     const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
     launch_fused3d(g, ctx->ftiles, true, fv, ctx->ead32, ctx->a32, ctx->c32, ctx->K32,
                    ctx->rowbits, r0, s);
