@@ -624,6 +624,32 @@ __device__ __forceinline__ void fused_origin(const Tiles& t, const Geo& g, int u
     kend = min(k0 + kz, g.nz + 1);
 }
 
+// Work items of one fused launch.  As in tile_range, XCD x (workgroups
+// b = x mod 8) takes one contiguous eighth [t0, t1) of the item list.  A
+// workgroup's first two items are fixed (items t0 + slot and t0 + slot + nblk,
+// slot = b / 8, nblk workgroups on the XCD); its later items come from its
+// XCD's counter in list order, so that the workgroups whose items hold few
+// active rows take more of them (a fixed stride left the busiest workgroup
+// with about 1.3x the mean work at 256^3).  The first claim is made during
+// the second item, when the workgroups no longer start in step, and a short
+// list never touches the counter.  The counters
+// alternate by launch parity: launch k takes from slot k & 1 and clears slot
+// (k + 1) & 1, which launch k - 1 used and launch k + 1 takes from.  The
+// first launch of a solve keeps the fixed stride, so a solve never depends on
+// counters left by an earlier one; so do grids of fewer than 8 workgroups.
+struct FusedQueue {
+    int t0, t1, first, step;   // the XCD's range, first item and stride (nblk)
+    unsigned* ctr;             // the XCD's counter, or null: fixed stride
+};
+__device__ __forceinline__ FusedQueue fused_queue(int count, unsigned* wq, int kidx, bool dyn) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G < 8) return FusedQueue{0, count, b, G, nullptr};
+    const int x = b & 7, slot = b >> 3;
+    const int nblk = (G - x + 7) >> 3;
+    const int t0 = (int)((long long)count * x / 8), t1 = (int)((long long)count * (x + 1) / 8);
+    return FusedQueue{t0, t1, t0 + slot, nblk, dyn ? wq + 8 * (kidx & 1) + x : nullptr};
+}
+
 template <typename T, int NS>
 struct FusedOwn {
     T r[NS], q[NS], P[NS], e[NS], a[NS], x[NS];   // P = a p, e = a D^-1
@@ -643,7 +669,8 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                                                     const T* __restrict__ a,
                                                     const T* __restrict__ c,
                                                     const T* __restrict__ K,
-                                                    const RowBits* __restrict__ rows, RedArgs ra) {
+                                                    const RowBits* __restrict__ rows,
+                                                    unsigned* __restrict__ wq, RedArgs ra) {
     constexpr int FNS = 6 / G, FNT = G * FNA;   // slices and threads per anchor / workgroup
     Scalars* sc = ra.sc;
     const int kidx = ra.kidx;
@@ -656,6 +683,8 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
     T* __restrict__ q_out = static_cast<T*>(v.q[pout]);
     T* __restrict__ x = static_cast<T*>(v.x);
 
+    // clear the work-queue slot of the next launch (before any early return)
+    if (blockIdx.x == 0 && threadIdx.x < 8) wq[8 * ((kidx + 1) & 1) + threadIdx.x] = 0u;
     // totals of the previous launch -> stop decision, alpha_{k-1}, beta_k
     PartialLoads<5, FNT, 2 / G> pl;
     if (!INIT) pl.load(ra.part_in, ra.nb_in);
@@ -710,6 +739,7 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
     // plane parity with G = 2 (128 VGPRs leave no room for them)
     constexpr int NOWN = G == 2 ? FNT : 1;
     __shared__ T sOwn[2][4][FNS][NOWN];
+    __shared__ int sNext;   // the item claimed from the work queue
     const unsigned NPB = (unsigned)g.NP * 4u;   // bytes of a slice (6 slices < 4 GiB)
     const int tid = threadIdx.x;
     // slice group (uniform per wave) and anchor of the plane
@@ -743,8 +773,10 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
     constexpr int qx = FNS - 3;
     constexpr int NF = (FFX * FFY + FNT - 1) / FNT;
     double rz_n = 0.0, rr_n = 0.0, pq_n = 0.0, qz_n = 0.0, qdq_n = 0.0;
-    const TileRange trg = tile_range(ft.items());
-    for (int wtile = trg.first; wtile < trg.end; wtile += trg.step) {
+    // with two threads per anchor the list is split in z and holds at most one
+    // item per workgroup, so that shape never claims
+    const FusedQueue fq = fused_queue(ft.items(), wq, kidx, !INIT && G == 1);
+    for (int wtile = fq.first; wtile < fq.t1;) {
         int xt, j0, k0, kend;
         fused_origin(ft, g, wtile, xt, j0, k0, kend);
         const int i0 = xt * FTX;
@@ -752,6 +784,7 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
         const int ih = i0 - 1 + hli, jh = j0 - 1 + hlj;
         // this thread also owns anchor (nx, jh) of the folded column
         const bool xown = xrole && xt == ft.ntx - 1 && jh <= g.ny;
+        const bool first_round = wtile < fq.t0 + fq.step;   // the next item is fixed
         __syncthreads();   // LDS of the previous item is no longer read
         for (int e = tid; e < (kend - k0 + 2) * FHY * 3; e += FNT) {
             const int pl = e / (FHY * 3), rw = (e / 3) % FHY, part = e % 3;
@@ -940,12 +973,16 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
         FusedHalo<T, FNS> Fh;
         T Ku[NF], Kv[NF], Kw[NF], Cc[FNS];
         __syncthreads();   // row bits of this item in LDS
+        // claim the next item now: the reply arrives with the prologue's loads
+        unsigned claim = 0u;
+        if (fq.ctr && !first_round && tid == 0) claim = atomicAdd(fq.ctr, 1u);
         fetch(k0 - 1, Fo, Fh);
         fetchK(k0 - 1, Ku, Kv, Kw);
         commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext, mnext, Cc);
         fetch(k0, Fo, Fh);
         commit(k0, Fo, Fh, vcur, acur, zcur, dcur, mcur, Cc);
         fetch(k0 + 1, Fo, Fh);
+        if (fq.ctr && tid == 0) sNext = (int)claim;
         __syncthreads();
         faces(k0 - 1, Ku, Kv, Kw);
         fetchK(k0, Ku, Kv, Kw);
@@ -1036,6 +1073,10 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
             }
             mcur = mnext;
         }
+        // next item: the fixed stride, or the claimed one after the XCD's two
+        // fixed rounds (sNext is rewritten only after the next item's first
+        // barrier)
+        wtile = (!fq.ctr || first_round) ? wtile + fq.step : fq.t0 + 2 * fq.step + sNext;
     }
     double vv[5] = {rz_n, pq_n, qz_n, qdq_n, rr_n};
     block_partial<5, FNT>(vv, ra.part_out, gridDim.x, blockIdx.x);
@@ -1321,23 +1362,23 @@ int fused3d_grid(int count) {
 
 void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v,
                     const float* ead, const float* a, const float* c, const float* K,
-                    const RowBits* rows, const RedArgs& ra, hipStream_t s) {
+                    const RowBits* rows, unsigned* wq, const RedArgs& ra, hipStream_t s) {
     if (ft.count <= 0) return;
     const dim3 gs(fused3d_grid(ft.items()));
     if (ft.split >= VFS_FUSED3_PAIR_SPLIT) {
         if (init)
             hipLaunchKernelGGL((k_fused3d<float, true, 2>), gs, dim3(2 * FNA), 0, s, g, ft, v,
-                               ead, a, c, K, rows, ra);
+                               ead, a, c, K, rows, wq, ra);
         else
             hipLaunchKernelGGL((k_fused3d<float, false, 2>), gs, dim3(2 * FNA), 0, s, g, ft, v,
-                               ead, a, c, K, rows, ra);
+                               ead, a, c, K, rows, wq, ra);
     } else {
         if (init)
             hipLaunchKernelGGL((k_fused3d<float, true, 1>), gs, dim3(FNA), 0, s, g, ft, v, ead,
-                               a, c, K, rows, ra);
+                               a, c, K, rows, wq, ra);
         else
             hipLaunchKernelGGL((k_fused3d<float, false, 1>), gs, dim3(FNA), 0, s, g, ft, v, ead,
-                               a, c, K, rows, ra);
+                               a, c, K, rows, wq, ra);
     }
 }
 

@@ -236,7 +236,7 @@ int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
     const FusedVecs fv{ctx->x32, {ctx->z32, ctx->r32}, {ctx->p032, ctx->p132}, {ctx->q32, ctx->f32b}};
     const RedArgs r0{ctx->sc, nullptr, 0, part[0], 0, 0};
     launch_fused3d(g, ctx->ftiles, true, fv, ctx->ead32, ctx->a32, ctx->c32, ctx->K32,
-                   ctx->rowbits, r0, s);
+                   ctx->rowbits, ctx->counter, r0, s);
     int chunk = 8;
     int kidx = 1;
     for (;;) {
@@ -245,7 +245,7 @@ int run_chunks_fused3d(vfs_ctx* ctx, bool set_bb, Scalars* out) {
                              (set_bb && kidx == 1) ? 1 : 0};
             if (ctx->prof && k == 1) HIPCHK(hipEventRecord(ctx->pev[0], s));
             launch_fused3d(g, ctx->ftiles, false, fv, ctx->ead32, ctx->a32, ctx->c32, ctx->K32,
-                           ctx->rowbits, ra, s);
+                           ctx->rowbits, ctx->counter, ra, s);
         }
         if (ctx->prof) HIPCHK(hipEventRecord(ctx->pev[1], s));
         HIPCHK(hipGetLastError());

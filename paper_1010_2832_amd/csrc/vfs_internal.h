@@ -247,7 +247,7 @@ struct vfs_ctx {
     // reductions
     double* partials = nullptr;  // per-workgroup partial sums: regions A, B, R
     long long capA = 0, capB = 0;
-    unsigned* counter = nullptr;
+    unsigned* counter = nullptr;     // 3D: work-queue counters of the fused iteration
     vfs::Scalars* sc = nullptr;      // device
     vfs::Scalars* sc_host = nullptr; // pinned mirror
     int* flag = nullptr;             // device: input validation flag
@@ -415,11 +415,13 @@ int apply3d_grid(int count, int word);
 int dir3d_grid(int count, int word);
 // one launch per Jacobi-PCG iteration in 3D (FP32), k_apply3d.hip
 // over the work tiles of fused_tile_dims (the list launch_fused_tiles builds
-// from the tile flags), skipping the rows of rowbits without an active sample
+// from the tile flags), skipping the rows of rowbits without an active sample;
+// wq: 16 work-queue counters (two slots of one per XCD), zero before the first
+// solve, kept by the launches themselves afterwards
 int fused3d_grid(int count);
 void launch_fused3d(const Geo& g, const Tiles& ft, bool init, const FusedVecs& v,
                     const float* ead, const float* a, const float* c, const float* K,
-                    const RowBits* rows, const RedArgs& ra, hipStream_t s);
+                    const RowBits* rows, unsigned* wq, const RedArgs& ra, hipStream_t s);
 void fused_tile_dims(const Geo& g, int& ntx, int& nty, int& ntz);
 void launch_fused_tiles(const Geo& g, const int* tile_flags, int* flags, int* list, int* count,
                         hipStream_t s);
