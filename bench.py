@@ -448,10 +448,17 @@ def hbm_copy_probe(mib=1024, reps=3):
     n = mib * 1024 * 1024 // 4
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
-    for _ in range(reps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
         torch.add(x, 0.0, out=y)
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps}),
+    ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+    # the copy's own rate (read + write) beside the 8 TB/s peak: what a plain
+    # streaming kernel reaches on this GPU
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "reps": reps,
+                      "copy_ms": ms, "copy_tb_per_s_best": 8 * n / min(ms) / 1e9}),
           flush=True)
 
 

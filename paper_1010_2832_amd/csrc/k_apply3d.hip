@@ -473,7 +473,7 @@ __global__ __launch_bounds__(NT) void k_dir3d_pipe(Geo g, Tiles tl, const T* __r
             __syncthreads();
             faces(k, Ku, Kv, Kw);
             T Cn[5];
-            fetchK(k + 1, Ku, Kv, Kw);
+            if (k + 1 < kend) fetchK(k + 1, Ku, Kv, Kw);   // no faces after the last plane
             fetchC(k + 1, Cn);
             __syncthreads();
             if (io <= g.nx && jo <= g.ny) {
@@ -994,7 +994,7 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
             if (k + 2 <= kend) fetch(k + 2, Fo, Fh);
             __syncthreads();
             faces(k, Ku, Kv, Kw);
-            fetchK(k + 1, Ku, Kv, Kw);
+            if (k + 1 < kend) fetchK(k + 1, Ku, Kv, Kw);   // no faces after the last plane
             __syncthreads();
             if (mcur) {
                 const int sk = k & 1, sp = (k - 1) & 1, sn = (k + 1) & 1;

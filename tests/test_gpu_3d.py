@@ -115,6 +115,38 @@ def test_step_mixed_3d(name):
     assert st["n_tile_samples"] == expected_tile_samples(asm, (64, 4, 8))
 
 
+def test_mixed_work_queue_matches_fp64():
+    """A grid whose fused work list outlasts two fixed rounds of the resident
+    grid, so that the mixed iteration's workgroups claim items from the
+    per-XCD counters: the mixed step must give the FP64 step's velocity (the
+    FP64 path has no work queue; the oracle cannot solve this size in a test)
+    to the mixed bar, on two consecutive solves (the counters carry over)."""
+    import torch
+    from paper_1010_2832_amd import vfstokes as V
+    case = cases.pool3d(192, seed=9)
+    _banner("work queue: pool3d 192 FP64 step")
+    c64 = gpu_run(case, precision=0, tol=1e-9)
+    s64 = c64.vfs_get_stats()
+    u64 = np.concatenate([q.ravel() for q in c64.vfs_get_velocity()])
+    tiles = s64["n_tile_samples"] // (64 * 4 * 8 * 6)
+    grid = 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    # the fused list drops the tiles of the folded wall column (one x tile in
+    # four at n = 192); more than two rounds of the grid must remain
+    assert tiles * 3 // 4 > 2 * grid, (tiles, grid)
+    c32 = V.context_from_case(case, precision=1, tol=1e-9, max_iter=200000)
+    for rep in range(2):
+        _banner(f"work queue: pool3d 192 mixed step, solve {rep}")
+        c32.vfs_set_velocity(case["u"])
+        c32.vfs_step(case["dt"])
+        s32 = c32.vfs_get_stats()
+        u32 = np.concatenate([q.ravel() for q in c32.vfs_get_velocity()])
+        err = np.abs(u32 - u64).max() / np.abs(u64).max()
+        _banner(f"  tiles {tiles} grid {grid} iters {s32['iterations']} rel_res {s32['rel_residual']:.2e} "
+                f"vel vs FP64 {err:.2e}")
+        assert s32["status"] == 0 and s32["rel_residual"] <= 1e-9
+        assert err <= 1e-4
+
+
 def test_no_liquid_3d():
     c = _random3d(9, 8, 7, 9)
     c["phi_l"] = np.ones_like(c["phi_l"])
