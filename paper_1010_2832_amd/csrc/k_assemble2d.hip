@@ -17,8 +17,8 @@ namespace {
 
 enum : uint8_t { FK = 1, FBAD = 2, FINV = 4 };
 
-__device__ __forceinline__ double rho_face(const Geo& g, const double* rho, long long o_lo,
-                                           long long o_hi, bool lo_in, bool hi_in) {
+__device__ __forceinline__ double rho_face(const double* rho, long long o_lo, long long o_hi,
+                                           bool lo_in, bool hi_in) {
     if (lo_in && hi_in) return (rho[o_lo] + rho[o_hi]) * 0.5;
     return lo_in ? rho[o_lo] : rho[o_hi];
 }
@@ -47,7 +47,7 @@ __global__ void k_face2d(Geo g, double dt, double g0, double g1, const double* _
         const double wfe = inval ? 0.0 : wf;
         const bool kp = wfe > 0.0 && wl > 0.0;
         const bool bad = wfe > 0.0 && wl == 0.0;
-        const double r = rho_face(g, rho, g.idx(i - 1, j), o, i > 0, i < g.nx);
+        const double r = rho_face(rho, g.idx(i - 1, j), o, i > 0, i < g.nx);
         WF[NP + o] = wfe;
         rhof[o] = r;
         K[o] = kp ? sK * (wfe / (r * wl)) : 0.0;
@@ -64,19 +64,13 @@ __global__ void k_face2d(Geo g, double dt, double g0, double g1, const double* _
         const double wfe = inval ? 0.0 : wf;
         const bool kp = wfe > 0.0 && wl > 0.0;
         const bool bad = wfe > 0.0 && wl == 0.0;
-        const double r = rho_face(g, rho, g.idx(i, j - 1), o, j > 0, j < g.ny);
+        const double r = rho_face(rho, g.idx(i, j - 1), o, j > 0, j < g.ny);
         WF[2 * NP + o] = wfe;
         rhof[NP + o] = r;
         K[NP + o] = kp ? sK * (wfe / (r * wl)) : 0.0;
         fflag[NP + o] = (uint8_t)((kp ? FK : 0) | (bad ? FBAD : 0) | (inval ? FINV : 0));
         ustar[NP + o] = u[NP + o] + dt * g1;
     }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
 }
 
 // One thread per anchor: cell (p, tau_xx) and node (tau_xy) coefficients,

@@ -67,7 +67,7 @@ __device__ __forceinline__ bool grid_barrier(BatchCtl* ctl, unsigned nblocks) {
             }
         }
         if (!advanced) {
-            const unsigned long long deadline = wall_clock64() + ctl->spin_ticks;
+            const long long deadline = wall_clock64() + (long long)ctl->spin_ticks;
             // relaxed polling: coherent loads without cache invalidation
             while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
                    my_gen) {
