@@ -49,9 +49,6 @@ int dalloc(vfs_ctx* ctx, T** p, long long n) {
 long long node_count(const Geo& g) {
     return (long long)(g.nx + 1) * (g.ny + 1) * (g.dim == 3 ? g.nz + 1 : 1);
 }
-long long cell_count(const Geo& g) {
-    return (long long)g.nx * g.ny * (g.dim == 3 ? g.nz : 1);
-}
 long long sub_count(const Geo& g) {
     return (long long)(2 * g.nx) * (2 * g.ny) * (g.dim == 3 ? 2 * g.nz : 1);
 }
