@@ -444,7 +444,10 @@ int solve_mixed(vfs_ctx* ctx, const double* b, double* x) {
             status = VFS_ENOTCONV;
             break;
         }
-        const double tol_in = std::min(0.5, std::max(0.5 * ctx->tol * bnorm / rho, 1e-5));
+        // each FP32 pass reduces its residual at most 1e-4: beyond that, its
+        // rounding slows the recurrence more than a fresh pass on the FP64
+        // residual costs
+        const double tol_in = std::min(0.5, std::max(0.5 * ctx->tol * bnorm / rho, 1e-4));
         launch_scale_to_f32(g, ctx->r, ctx->r32, ctx->sc + 1, ctx->stream);
         launch_cg_init<float>(g, ctx->r32, ctx->x32, ctx->r32, ctx->dinv32, nullptr, tol_in,
                               ctx->max_iter - total, ctx->sc, P.B, ctx->stream);
