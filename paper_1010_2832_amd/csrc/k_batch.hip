@@ -232,6 +232,15 @@ __device__ double tile_resid(const Geo& g, int i0, int j0, const double* __restr
 // Otherwise r = r_{k-1} - alpha q_{k-1} on the tile and its halo, x += alpha
 // p_{k-1} at the own anchors, z = D^-1 r, p = z + beta p_{k-1}, q = A p.
 // Adds this thread's shares of (r.z, p.q, q.z, q.D^-1 q, r.r) to v.
+//
+// The faces need a p at every position of the tile and its halo, so the
+// vectors are kept weighted, as in the fused 3D iteration: the direction as
+// P = a p, the residual and A p as R = e r and Q = e q with e = a D^-1.
+// Then a p_k = R_{k-1} - alpha Q_{k-1} + beta P_{k-1} takes three loads per
+// halo position (R, Q, P) instead of five (r, q, p, D^-1, a).  The own
+// anchors read e and a as well and form r = R / e, z = R / a, p = P / a and
+// D^-1 = e / a.  INIT reads the plain residual r_0 from the second r buffer
+// and writes R_0 = e r_0 to the first.
 template <int BX, int BY, bool INIT>
 __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float beta, int k,
                            float* lds, double (&v)[5]) {
@@ -246,14 +255,14 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
     float* const rv[2] = {P.r32, P.r32b};
     float* const pv[2] = {P.p0, P.p1};
     float* const qv[2] = {P.q32, P.q32b};
-    const float* __restrict__ r_in = rv[INIT ? 0 : pin];
+    const float* __restrict__ r_in = rv[INIT ? 1 : pin];
     const float* __restrict__ q_in = qv[pin];
     const float* __restrict__ p_in = pv[pin];
     float* __restrict__ r_out = rv[pout];
     float* __restrict__ p_out = pv[pout];
     float* __restrict__ q_out = qv[pout];
     float* __restrict__ x = P.x32;
-    const float* __restrict__ dinv = P.dinv;
+    const float* __restrict__ ead = P.ead;   // e = a D^-1
     const float* __restrict__ a = P.a;
     const float* __restrict__ c = P.c;
     const float* __restrict__ K = P.K;
@@ -266,7 +275,7 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
 #define G2(f_, y_, x_) sG[((f_) * FY + (y_)) * FX + (x_)]
     // own anchors (i0 + tx, j0 + ty): the thread that forms p, z there also
     // forms q there, so only a p crosses threads (through LDS)
-    float Rr[RPT][3], Dd[RPT][3], Qq[RPT][3], Pp[RPT][3], Aa[RPT][3], Xx[RPT][3], Co[RPT][2];
+    float Rr[RPT][3], Ee[RPT][3], Qq[RPT][3], Pp[RPT][3], Aa[RPT][3], Xx[RPT][3], Co[RPT][2];
     bool own[RPT];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
@@ -277,10 +286,10 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const long long os = o + s * NP;
-            Rr[rr][s] = Dd[rr][s] = Qq[rr][s] = Pp[rr][s] = Aa[rr][s] = Xx[rr][s] = 0.f;
+            Rr[rr][s] = Ee[rr][s] = Qq[rr][s] = Pp[rr][s] = Aa[rr][s] = Xx[rr][s] = 0.f;
             if (in) {
                 Rr[rr][s] = r_in[os];
-                Dd[rr][s] = dinv[os];
+                Ee[rr][s] = ead[os];
                 Aa[rr][s] = a[os];
                 if (!INIT) {
                     Qq[rr][s] = q_in[os];
@@ -294,7 +303,7 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
     }
     // halo ring: rows lj = 0 and HY - 1 (corners included), then columns
     // li = 0 and HX - 1; position h = tid + m NT
-    float Rh[NHR][3], Dh[NHR][3], Qh[NHR][3], Ph[NHR][3], Ah[NHR][3];
+    float Rh[NHR][3], Eh[NHR][3], Qh[NHR][3], Ph[NHR][3];
     int hli[NHR], hlj[NHR];
 #pragma unroll
     for (int m = 0; m < NHR; ++m) {
@@ -318,12 +327,12 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             const long long os = o + s * NP;
-            Rh[m][s] = Dh[m][s] = Qh[m][s] = Ph[m][s] = Ah[m][s] = 0.f;
+            Rh[m][s] = Eh[m][s] = Qh[m][s] = Ph[m][s] = 0.f;
             if (in) {
                 Rh[m][s] = r_in[os];
-                Dh[m][s] = dinv[os];
-                Ah[m][s] = a[os];
-                if (!INIT) {
+                if (INIT) {
+                    Eh[m][s] = ead[os];   // to weight the plain residual
+                } else {
                     Qh[m][s] = q_in[os];
                     Ph[m][s] = p_in[os];
                 }
@@ -343,30 +352,33 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
             if (iv >= 0 && iv < g.nx && jv <= g.ny) Kv[m] = K[NP + g.idx(iv, jv)];
         }
     }
-    // r_k, z_k, p_k on the tile and its halo; own anchors also store r, x, p
-    float Vo[RPT][3], Zo[RPT][3];
+    // R_k and a p_k on the tile and its halo; own anchors also store R, x, P
+    // and keep p, z, D^-1
+    float Vo[RPT][3], Zo[RPT][3], Dd[RPT][3];
 #pragma unroll
     for (int rr = 0; rr < RPT; ++rr) {
         const int ty = tid / BX + rr * (NT / BX);
         const long long o = own[rr] ? g.idx(i0 + tx, j0 + ty) : 0;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const float rn = INIT ? Rr[rr][s] : Rr[rr][s] - alpha * Qq[rr][s];
-            const float zn = Dd[rr][s] * rn;
-            const float pn = INIT ? zn : zn + beta * Pp[rr][s];
+            const float Rn = INIT ? Ee[rr][s] * Rr[rr][s] : Rr[rr][s] - alpha * Qq[rr][s];
+            const float W = INIT ? Rn : Rn + beta * Pp[rr][s];   // a p_k
+            const float ia = Aa[rr][s] != 0.f ? 1.f / Aa[rr][s] : 0.f;
+            const float ie = Ee[rr][s] != 0.f ? __builtin_amdgcn_rcpf(Ee[rr][s]) : 0.f;
+            const float rn = INIT ? Rr[rr][s] : Rn * ie;   // r_k (for the partials only)
+            const float zn = Rn * ia;
             if (own[rr]) {
                 const long long os = o + s * NP;
-                if (!INIT) {
-                    r_out[os] = rn;
-                    x[os] = Xx[rr][s] + alpha * Pp[rr][s];
-                }
-                p_out[os] = pn;
+                r_out[os] = Rn;
+                if (!INIT) x[os] = Xx[rr][s] + alpha * (Pp[rr][s] * ia);
+                p_out[os] = W;
                 v[0] += (double)rn * (double)zn;
                 v[4] += (double)rn * (double)rn;
             }
-            Vo[rr][s] = pn;
+            Vo[rr][s] = W * ia;
             Zo[rr][s] = zn;
-            L3(sW, s, ty + 1, tx + 1) = Aa[rr][s] * pn;
+            Dd[rr][s] = Ee[rr][s] * ia;
+            L3(sW, s, ty + 1, tx + 1) = W;
         }
     }
 #pragma unroll
@@ -374,9 +386,8 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
         if (tid + m * NT >= NH) continue;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
-            const float rn = INIT ? Rh[m][s] : Rh[m][s] - alpha * Qh[m][s];
-            const float pn = INIT ? Dh[m][s] * rn : Dh[m][s] * rn + beta * Ph[m][s];
-            L3(sW, s, hlj[m], hli[m]) = Ah[m][s] * pn;
+            const float Rn = INIT ? Eh[m][s] * Rh[m][s] : Rh[m][s] - alpha * Qh[m][s];
+            L3(sW, s, hlj[m], hli[m]) = INIT ? Rn : Rn + beta * Ph[m][s];
         }
     }
     __syncthreads();
@@ -406,7 +417,7 @@ __device__ void tile_fused(const BProb& P, int i0, int j0, float alpha, float be
             y[2] = Aa[rr][2] * ((gu0 - gum) + (gv0 - gvm)) + Co[rr][1] * Vo[rr][2];
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
-                q_out[o + s * NP] = y[s];
+                q_out[o + s * NP] = (Dd[rr][s] * Aa[rr][s]) * y[s];   // e q
                 const double yd = y[s];
                 v[1] += (double)Vo[rr][s] * yd;
                 v[2] += (double)Zo[rr][s] * yd;
@@ -562,7 +573,8 @@ __global__ __launch_bounds__(NT, 2) void k_batch_pcg(BatchArgs A) {
     const int wb = (int)blockIdx.x, ws = (int)G;
     const int nitems = *A.nlive;
 
-    // r32 = r64 / |r64|, x32 = 0 on the tile (start of an inner solve)
+    // r = r64 / |r64| into the second r buffer (the INIT iteration weights it
+    // into the first), x32 = 0 on the tile (start of an inner solve)
     auto init_inner = [&](const BProb& P, int i0, int j0, double rho2) {
         const double inv = rho2 > 0.0 ? 1.0 / sqrt(rho2) : 0.0;
         for (int e = threadIdx.x; e < BX * BY; e += NT) {
@@ -572,7 +584,7 @@ __global__ __launch_bounds__(NT, 2) void k_batch_pcg(BatchArgs A) {
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 const long long os = o + s * P.g.NP;
-                P.r32[os] = (float)(P.r64[os] * inv);
+                P.r32b[os] = (float)(P.r64[os] * inv);
                 P.x32[os] = 0.f;
             }
         }

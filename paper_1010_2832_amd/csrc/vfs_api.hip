@@ -695,7 +695,7 @@ int assemble_internal(vfs_ctx* ctx, double dt) {
         launch_to_f32(ctx->a, ctx->a32, ns, s);
         launch_to_f32(ctx->c, ctx->c32, ns, s);
         launch_to_f32(ctx->dinv, ctx->dinv32, ns, s);
-        if (g.dim == 3) launch_mul_to_f32(ctx->a, ctx->dinv, ctx->ead32, ns, s);
+        launch_mul_to_f32(ctx->a, ctx->dinv, ctx->ead32, ns, s);
     }
     HIPCHK(hipGetLastError());
     ctx->assembled = true;
@@ -893,7 +893,7 @@ int vfs_create(vfs_ctx** out, int dim, int nx, int ny, int nz, double h, const d
     ALLOC(ctx->a32, ns * NP);
     ALLOC(ctx->c32, ns * NP);
     ALLOC(ctx->dinv32, ns * NP);
-    if (dim == 3) ALLOC(ctx->ead32, ns * NP);
+    ALLOC(ctx->ead32, ns * NP);
     ALLOC(ctx->x, ns * NP);
     ALLOC(ctx->r, ns * NP);
     ALLOC(ctx->p0, ns * NP);

@@ -16,6 +16,7 @@ struct BProb {
     float *x32, *r32, *p0, *p1, *q32;
     float *r32b, *q32b;           // second r and q buffers (iteration parity)
     const float *a, *c, *K, *dinv;
+    const float* ead;             // e = a D^-1, the weight of the residual and A p
     double *x64, *r64;
     const double *a64, *c64, *K64, *b64;
 };

@@ -181,6 +181,7 @@ int build_items(vfs_batch* b) {
         P.c = c->c32;
         P.K = c->K32;
         P.dinv = c->dinv32;
+        P.ead = c->ead32;
         P.x64 = c->x;
         P.r64 = c->r;
         P.a64 = c->a;
