@@ -58,3 +58,19 @@ def test_sweep_caps_picks_and_caches(tmp_path, monkeypatch):
     assert autotune.tune(b3, cache_path=cache)["cached"] is False and b3.timed
     b4 = FakeBatch([(64, 64), (96, 96)])
     assert autotune.tune(b4, cache_path=cache, use_cache=False)["cached"] is False and b4.timed
+
+
+def test_near_ties_go_to_the_larger_tile(tmp_path, monkeypatch):
+    """Entries within 1% of the fastest probe: the largest tile area wins;
+    beyond 1% the fastest wins."""
+    monkeypatch.setattr(autotune, "V", fake_lib())
+    monkeypatch.setattr(autotune, "_device_name", lambda: "dev")
+    monkeypatch.setitem(TIMES, (4, 2), 0.5)            # 64x12, the fastest probe
+    monkeypatch.setitem(TIMES, (5, 2), 0.5 * 1.005)    # 64x16, 0.5% slower: a tie
+    b = FakeBatch([(64, 64)])
+    res = autotune.tune(b, cache_path=None, use_cache=False)
+    assert list(res["shape"]) == [64, 16] and b.applied == (5, 2)
+    monkeypatch.setitem(TIMES, (5, 2), 0.5 * 1.02)     # 2% slower: 64x12 wins
+    b2 = FakeBatch([(64, 64)])
+    res2 = autotune.tune(b2, cache_path=None, use_cache=False)
+    assert list(res2["shape"]) == [64, 12] and b2.applied == (4, 2)
