@@ -823,8 +823,11 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                 const unsigned sb = (unsigned)s * NPB;   // slice offset in bytes (uniform)
                 const bool lo = (o.m >> s) & 1u, lh = (h.m >> s) & 1u;
                 o.r[q] = lo ? ld_at(r_in, oo + sb) : T(0);
-                o.e[q] = lo ? ld_at(ead, oo + sb) : T(0);
-                o.a[q] = lo ? ld_at(a, oo + sb) : T(0);
+                // a p needs neither a nor e outside the item's own anchors (its
+                // z-halo planes, the rows past the grid), except to weight the
+                // plain residual of the first launch
+                o.e[q] = (lo && (INIT || own)) ? ld_at(ead, oo + sb) : T(0);
+                o.a[q] = (lo && own) ? ld_at(a, oo + sb) : T(0);
                 o.q[q] = (lo && !INIT) ? ld_at(q_in, oo + sb) : T(0);
                 o.P[q] = (lo && !INIT) ? ld_at(p_in, oo + sb) : T(0);
                 o.x[q] = (lo && own && !INIT) ? ld_at(x, oo + sb) : T(0);
