@@ -663,6 +663,12 @@ struct FusedHalo {
     unsigned m;
 };
 
+// R, Q and P of one plane: all that a p = R - alpha Q + beta P needs
+template <typename T, int NS>
+struct FusedW {
+    T r[NS], q[NS], P[NS];
+};
+
 template <typename T, bool INIT, int G>
 __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, FusedVecs v,
                                                     const T* __restrict__ ead,
@@ -923,6 +929,37 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
                 }
             }
         };
+        // the plane below the item: outside the first launch only a p is formed
+        // there, from three loads per sample, so its loads need not wait for
+        // those of plane k0
+        auto fetchW = [&](int kk, FusedW<T, FNS>& o, FusedW<T, FNS>& h) {
+            const int pl = kk - k0 + 1;
+            const unsigned mo = io <= g.nx + 1 ? half_bits(sRB[pl][ty + 1][1], tx) & gmask : 0u;
+            const unsigned oo = boff3(g, io, jo, kk, mo != 0u);
+            const unsigned mh =
+                (hrole && ih <= g.nx + 1) ? half_bits(sRB[pl][hlj][hdt + 1], hlane) & gmask : 0u;
+            const unsigned oh = boff3(g, ih, jh, kk, mh != 0u);
+#pragma unroll
+            for (int q = 0; q < FNS; ++q) {
+                const int s = s0 + q;
+                const unsigned sb = (unsigned)s * NPB;
+                const bool lo = (mo >> s) & 1u, lh = (mh >> s) & 1u;
+                o.r[q] = lo ? ld_at(r_in, oo + sb) : T(0);
+                o.q[q] = lo ? ld_at(q_in, oo + sb) : T(0);
+                o.P[q] = lo ? ld_at(p_in, oo + sb) : T(0);
+                h.r[q] = lh ? ld_at(r_in, oh + sb) : T(0);
+                h.q[q] = lh ? ld_at(q_in, oh + sb) : T(0);
+                h.P[q] = lh ? ld_at(p_in, oh + sb) : T(0);
+            }
+        };
+        auto commitW = [&](int kk, const FusedW<T, FNS>& o, const FusedW<T, FNS>& h) {
+            const int sl = kk & 1;
+#pragma unroll
+            for (int q = 0; q < FNS; ++q) {
+                sW[sl][s0 + q][ty + 1][tx + 1] = (o.r[q] - alpha * o.q[q]) + beta * o.P[q];
+                if (hrole) sW[sl][s0 + q][hlj][hli] = (h.r[q] - alpha * h.q[q]) + beta * h.P[q];
+            }
+        };
         auto fetchK = [&](int kk, T (&ku)[NF], T (&kv)[NF], T (&kw)[NF]) {
 #pragma unroll
             for (int m = 0; m < NF; ++m) {
@@ -979,10 +1016,18 @@ __global__ __launch_bounds__(G * FNA, 2 * G) void k_fused3d(Geo g, Tiles ft, Fus
         // claim the next item now: the reply arrives with the prologue's loads
         unsigned claim = 0u;
         if (fq.ctr && !first_round && tid == 0) claim = atomicAdd(fq.ctr, 1u);
-        fetch(k0 - 1, Fo, Fh);
-        fetchK(k0 - 1, Ku, Kv, Kw);
-        commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext, mnext, Cc);
-        fetch(k0, Fo, Fh);
+        if constexpr (INIT) {   // e weights the plain residual of plane k0 - 1 too
+            fetch(k0 - 1, Fo, Fh);
+            fetchK(k0 - 1, Ku, Kv, Kw);
+            commit(k0 - 1, Fo, Fh, vnext, anext, znext, dnext, mnext, Cc);
+            fetch(k0, Fo, Fh);
+        } else {
+            FusedW<T, FNS> Wo, Wh;
+            fetchW(k0 - 1, Wo, Wh);
+            fetchK(k0 - 1, Ku, Kv, Kw);
+            fetch(k0, Fo, Fh);
+            commitW(k0 - 1, Wo, Wh);
+        }
         commit(k0, Fo, Fh, vcur, acur, zcur, dcur, mcur, Cc);
         fetch(k0 + 1, Fo, Fh);
         if (fq.ctr && tid == 0) sNext = (int)claim;
